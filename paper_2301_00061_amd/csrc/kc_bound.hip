@@ -1,0 +1,300 @@
+// kc_bound.hip -- kc_lower_bound / kc_objective entry points, launch sizing
+// and the kernels that reduce the per-split partial results.
+#include <cmath>
+#include <cstdio>
+
+#include "kc_bound_impl.h"
+
+namespace kcb {
+kc_status launch_d0(int, int, int, bool, const BoundArgs &, int, size_t, hipStream_t);
+kc_status launch_d1(int, int, int, bool, const BoundArgs &, int, size_t, hipStream_t);
+kc_status launch_d2(int, int, int, bool, const BoundArgs &, int, size_t, hipStream_t);
+kc_status launch_d3(int, int, int, bool, const BoundArgs &, int, size_t, hipStream_t);
+kc_status launch_d4(int, int, int, bool, const BoundArgs &, int, size_t, hipStream_t);
+kc_status launch_d5(int, int, int, bool, const BoundArgs &, int, size_t, hipStream_t);
+kc_status launch_d6(int, int, int, bool, const BoundArgs &, int, size_t, hipStream_t);
+kc_status launch_d7(int, int, int, bool, const BoundArgs &, int, size_t, hipStream_t);
+kc_status launch_d8(int, int, int, bool, const BoundArgs &, int, size_t, hipStream_t);
+kc_status launch_obj64_d0(const Obj64Args &, int, size_t, hipStream_t);
+kc_status launch_obj64_d1(const Obj64Args &, int, size_t, hipStream_t);
+kc_status launch_obj64_d2(const Obj64Args &, int, size_t, hipStream_t);
+kc_status launch_obj64_d3(const Obj64Args &, int, size_t, hipStream_t);
+kc_status launch_obj64_d4(const Obj64Args &, int, size_t, hipStream_t);
+kc_status launch_obj64_d5(const Obj64Args &, int, size_t, hipStream_t);
+kc_status launch_obj64_d6(const Obj64Args &, int, size_t, hipStream_t);
+kc_status launch_obj64_d7(const Obj64Args &, int, size_t, hipStream_t);
+kc_status launch_obj64_d8(const Obj64Args &, int, size_t, hipStream_t);
+
+static kc_status dispatch(int d, int S, int NG, int KC, bool point, const BoundArgs &A, int grid,
+                          size_t lds, hipStream_t st) {
+  switch (d) {
+    case 1: return launch_d1(S, NG, KC, point, A, grid, lds, st);
+    case 2: return launch_d2(S, NG, KC, point, A, grid, lds, st);
+    case 3: return launch_d3(S, NG, KC, point, A, grid, lds, st);
+    case 4: return launch_d4(S, NG, KC, point, A, grid, lds, st);
+    case 5: return launch_d5(S, NG, KC, point, A, grid, lds, st);
+    case 6: return launch_d6(S, NG, KC, point, A, grid, lds, st);
+    case 7: return launch_d7(S, NG, KC, point, A, grid, lds, st);
+    case 8: return launch_d8(S, NG, KC, point, A, grid, lds, st);
+    default: return launch_d0(S, NG, KC, point, A, grid, lds, st);
+  }
+}
+
+static kc_status dispatch64(int d, const Obj64Args &A, int splits, size_t lds, hipStream_t st) {
+  switch (d) {
+    case 1: return launch_obj64_d1(A, splits, lds, st);
+    case 2: return launch_obj64_d2(A, splits, lds, st);
+    case 3: return launch_obj64_d3(A, splits, lds, st);
+    case 4: return launch_obj64_d4(A, splits, lds, st);
+    case 5: return launch_obj64_d5(A, splits, lds, st);
+    case 6: return launch_obj64_d6(A, splits, lds, st);
+    case 7: return launch_obj64_d7(A, splits, lds, st);
+    case 8: return launch_obj64_d8(A, splits, lds, st);
+    default: return launch_obj64_d0(A, splits, lds, st);
+  }
+}
+
+// Reduces the per-split partial keys. mode 0: lower bound (rounded down),
+// mode 1: float32 objective (rounded up).
+__global__ void k_bound_finalize(const uint64_t *part_key, int n_nodes, int splits,
+                                 const uint64_t *part_cand, int n_boxes, int mode, double rel,
+                                 double abs_, float *val_raw, double *val_bound, int64_t *argmax,
+                                 int64_t *cand) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_nodes) {
+    uint64_t key = 0;
+    for (int sp = 0; sp < splits; ++sp) {
+      const uint64_t v = part_key[(int64_t)sp * n_nodes + i];
+      key = v > key ? v : key;
+    }
+    const float v = key ? __uint_as_float((uint32_t)(key >> 32)) : 0.0f;
+    const uint32_t idx = key ? ~(uint32_t)(key & 0xffffffffu) : 0u;
+    if (val_raw) val_raw[i] = v;
+    if (argmax) argmax[i] = (int64_t)idx;
+    if (val_bound) {
+      const double vd = (double)v;
+      double r;
+      if (mode == 0) {
+        r = vd * (1.0 - rel) - abs_;
+        r = r > 0.0 ? r : 0.0;
+      } else {
+        r = vd * (1.0 + rel) + abs_;
+      }
+      val_bound[i] = r;
+    }
+  }
+  if (cand && i < n_boxes) {
+    uint64_t key = ~0ull;
+    for (int sp = 0; sp < splits; ++sp) {
+      const uint64_t v = part_cand[(int64_t)sp * n_boxes + i];
+      key = v < key ? v : key;
+    }
+    cand[i] = key == ~0ull ? -1 : (int64_t)(uint32_t)(key & 0xffffffffu);
+  }
+}
+
+__global__ void k_obj64_finalize(const double *part_val, const uint32_t *part_idx, int n_sets,
+                                 int splits, double *obj, int64_t *argmax) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n_sets) return;
+  double best = -1.0;
+  uint32_t bi = 0xffffffffu;
+  for (int sp = 0; sp < splits; ++sp) {
+    const double v = part_val[(int64_t)sp * n_sets + c];
+    const uint32_t ii = part_idx[(int64_t)sp * n_sets + c];
+    if (v > best || (v == best && ii < bi)) {
+      best = v;
+      bi = ii;
+    }
+  }
+  if (obj) obj[c] = best;
+  if (argmax) argmax[c] = bi == 0xffffffffu ? -1 : (int64_t)bi;
+}
+
+}  // namespace kcb
+
+using namespace kcb;
+
+static int dmax_of(int d) { return d <= 8 ? d : 16; }
+
+static int cand_kc(int k_max) {
+  if (k_max <= 4) return 4;
+  if (k_max <= 8) return 8;
+  if (k_max <= 16) return 16;
+  return 64;
+}
+
+std::vector<kc_tile> kc_bound_variants(int d, bool with_cand, int k_max) {
+  std::vector<kc_tile> v;
+  (void)d;
+  if (with_cand) {
+    const int kc = cand_kc(k_max);
+#define KCB_T3(SV, NGV, KCV) \
+  if (KCV == kc) v.push_back({SV, NGV, 8});
+    KCB_CAND_VARIANTS(KCB_T3)
+#undef KCB_T3
+  } else {
+#define KCB_T2(SV, NGV) v.push_back({SV, NGV, 8});
+    KCB_LB_VARIANTS(KCB_T2)
+#undef KCB_T2
+  }
+  // each shape at two occupancies
+  const size_t n0 = v.size();
+  for (size_t i = 0; i < n0; ++i) v.push_back({v[i].S, v[i].NG, 4});
+  return v;
+}
+
+kc_tile kc_default_tile(kc_handle *h, int d, bool with_cand, int n_nodes, int k_max, int64_t n) {
+  (void)h;
+  (void)n;
+  if (with_cand) return {k_max <= 8 ? 2 : 1, 1, 8};
+  if (n_nodes == 1) return {d <= 4 ? 8 : 4, 1, 8};
+  if (n_nodes <= 3) return {4, 2, 8};
+  if (n_nodes <= 7) return {4, 4, 8};
+  return {d <= 4 ? 4 : 2, 8, 8};
+}
+
+kc_status kc_launch_bound(kc_handle *h, const kc_points *p, int mode, int n_nodes, int n_boxes,
+                          int k_max, const int32_t *box_off, const float *lo, const float *hi,
+                          float *val_raw, double *val_bound, int64_t *argmax, int64_t *cand,
+                          const kc_tile &t0, hipStream_t st) {
+  const bool point = mode == 1;
+  const bool with_cand = cand != nullptr && !point;
+  kc_tile t = t0;
+  const int DM = dmax_of(p->d);
+  const int KC = with_cand ? cand_kc(k_max) : 0;
+  if (with_cand) {
+    // candidate variants exist for NG = 1 only
+    t.NG = 1;
+    if (KC >= 16) t.S = 1;
+  }
+  if (point) {
+    if (!((t.S == 4 && t.NG == 1) || (t.S == 2 && t.NG == 4) || (t.S == 2 && t.NG == 8)))
+      t = n_nodes <= 2 ? kc_tile{4, 1, t.bpc} : kc_tile{2, 4, t.bpc};
+  }
+  size_t lds = (size_t)t.NG * k_max * 2 * DM * sizeof(float);
+  while (lds > h->lds_per_block && t.NG > 1) {
+    t.NG /= 2;
+    lds = (size_t)t.NG * k_max * 2 * DM * sizeof(float);
+  }
+  KC_RETURN_IF(lds > h->lds_per_block, h, KC_EUNSUPPORTED, "boxes of one node exceed LDS");
+  const int n_groups = (n_nodes + t.NG - 1) / t.NG;
+  const int64_t tile = (int64_t)WG * t.S;
+  const int64_t target = (int64_t)h->n_cu * (t.bpc > 0 ? t.bpc : 8);
+  int64_t splits = (target + n_groups - 1) / n_groups;
+  if (splits < 1) splits = 1;
+  int64_t span = (p->n + splits - 1) / splits;
+  span = (span + tile - 1) / tile * tile;
+  splits = (p->n + span - 1) / span;
+  const int64_t grid = splits * n_groups;
+  KC_RETURN_IF(grid > 0x7fffffff, h, KC_EUNSUPPORTED, "grid too large");
+
+  const size_t part_bytes = (size_t)splits * n_nodes * 8;
+  const size_t cand_bytes = with_cand ? (size_t)splits * n_boxes * 8 : 0;
+  void *scr = nullptr;
+  kc_status s = kc_get_scratch(h, part_bytes + cand_bytes, &scr);
+  if (s != KC_OK) return s;
+
+  BoundArgs A;
+  A.x = p->x;
+  A.n = p->n;
+  A.ld = p->ld;
+  A.d = p->d;
+  A.n_nodes = n_nodes;
+  A.n_boxes = n_boxes;
+  A.k_max = k_max;
+  A.box_off = box_off;
+  A.lo = lo;
+  A.hi = hi;
+  A.n_groups = n_groups;
+  A.span = span;
+  A.part_key = (uint64_t *)scr;
+  A.part_cand = with_cand ? (uint64_t *)((char *)scr + part_bytes) : nullptr;
+  s = dispatch(p->d, t.S, t.NG, KC, point, A, (int)grid, lds, st);
+  KC_RETURN_IF(s != KC_OK, h, s, "no bound-kernel variant S=%d NG=%d KC=%d point=%d", t.S, t.NG,
+               KC, (int)point);
+  s = kc_check_launch(h, "k_bound");
+  if (s != KC_OK) return s;
+  const int fin = with_cand ? (n_nodes > n_boxes ? n_nodes : n_boxes) : n_nodes;
+  const double rel = kc_rel_margin(p->d) + 0x1p-50;
+  k_bound_finalize<<<(fin + 255) / 256, 256, 0, st>>>(A.part_key, n_nodes, (int)splits,
+                                                       A.part_cand, n_boxes, mode, rel,
+                                                       kc_abs_margin(p->d), val_raw, val_bound,
+                                                       argmax, with_cand ? cand : nullptr);
+  return kc_check_launch(h, "k_bound_finalize");
+}
+
+static std::string tune_lookup_key(const kc_points *p, const kc_nodes *m, bool cand) {
+  return kc_tune_key(p->d, cand, m->n_nodes, m->k_max, p->n);
+}
+
+extern "C" kc_status kc_lower_bound(kc_handle *h, const kc_points *pts, const kc_nodes *nodes,
+                                    float *lb_raw, double *lb_safe, int64_t *argmax,
+                                    int64_t *cand, void *stream) {
+  if (!h) return KC_EINVAL;
+  kc_status s = kc_validate_points(h, pts);
+  if (s != KC_OK) return s;
+  s = kc_validate_nodes(h, nodes, pts);
+  if (s != KC_OK) return s;
+  KC_RETURN_IF(!lb_raw && !lb_safe && !argmax && !cand, h, KC_EINVAL, "no output requested");
+  const bool wc = cand != nullptr;
+  kc_tile t;
+  auto it = h->tune.find(tune_lookup_key(pts, nodes, wc));
+  if (it != h->tune.end())
+    t = it->second;
+  else
+    t = kc_default_tile(h, pts->d, wc, nodes->n_nodes, nodes->k_max, pts->n);
+  return kc_launch_bound(h, pts, 0, nodes->n_nodes, nodes->n_boxes, nodes->k_max, nodes->box_off,
+                         nodes->lo, nodes->hi, lb_raw, lb_safe, argmax, cand, t,
+                         (hipStream_t)stream);
+}
+
+extern "C" kc_status kc_objective(kc_handle *h, const kc_points *pts, int32_t n_sets, int32_t k,
+                                  const float *centers, int32_t precision, double *obj,
+                                  int64_t *argmax, void *stream) {
+  if (!h) return KC_EINVAL;
+  kc_status s = kc_validate_points(h, pts);
+  if (s != KC_OK) return s;
+  KC_RETURN_IF(n_sets < 1, h, KC_EINVAL, "n_sets must be >= 1 (got %d)", n_sets);
+  KC_RETURN_IF(k < 1 || k > 64, h, KC_EINVAL, "k must be in [1,64] (got %d)", k);
+  KC_RETURN_IF(!centers, h, KC_EINVAL, "centers is NULL");
+  KC_RETURN_IF(precision != 32 && precision != 64, h, KC_EINVAL, "precision must be 32 or 64");
+  KC_RETURN_IF(!obj && !argmax, h, KC_EINVAL, "no output requested");
+  hipStream_t st = (hipStream_t)stream;
+  if (precision == 32) {
+    kc_tile t = n_sets <= 2 ? kc_tile{4, 1, 8} : kc_tile{2, 4, 8};
+    return kc_launch_bound(h, pts, 1, n_sets, n_sets * k, k, nullptr, centers, centers, nullptr,
+                           obj, argmax, nullptr, t, st);
+  }
+  const int DM = dmax_of(pts->d);
+  const int64_t target = (int64_t)h->n_cu * 8;
+  int64_t splits = (target + n_sets - 1) / n_sets;
+  int64_t span = (pts->n + splits - 1) / splits;
+  span = (span + WG - 1) / WG * WG;
+  splits = (pts->n + span - 1) / span;
+  KC_RETURN_IF(n_sets > 65535, h, KC_EUNSUPPORTED, "too many sets for the float64 objective");
+  const size_t vb = (size_t)splits * n_sets * sizeof(double);
+  const size_t ib = (size_t)splits * n_sets * sizeof(uint32_t);
+  void *scr = nullptr;
+  s = kc_get_scratch(h, vb + ib, &scr);
+  if (s != KC_OK) return s;
+  Obj64Args A;
+  A.x = pts->x;
+  A.n = pts->n;
+  A.ld = pts->ld;
+  A.d = pts->d;
+  A.n_sets = n_sets;
+  A.k = k;
+  A.centers = centers;
+  A.span = span;
+  A.part_val = (double *)scr;
+  A.part_idx = (uint32_t *)((char *)scr + vb);
+  const size_t lds = (size_t)k * DM * sizeof(double);
+  s = dispatch64(pts->d, A, (int)splits, lds, st);
+  if (s != KC_OK) return kc_fail(h, s, "float64 objective launch");
+  s = kc_check_launch(h, "k_obj64");
+  if (s != KC_OK) return s;
+  k_obj64_finalize<<<(n_sets + 255) / 256, 256, 0, st>>>(A.part_val, A.part_idx, n_sets,
+                                                          (int)splits, obj, argmax);
+  return kc_check_launch(h, "k_obj64_finalize");
+}

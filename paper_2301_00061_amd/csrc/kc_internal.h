@@ -1,0 +1,72 @@
+// kc_internal.h -- host-side internals shared by the libkc translation units:
+// the handle, scratch memory, error reporting, margin thresholds and the
+// launch-variant tables the autotuner picks from.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "kc.h"
+
+// One launch shape of the bound kernel.
+struct kc_tile {
+  int S;    // samples per lane per tile
+  int NG;   // nodes per workgroup (running maxima held in registers)
+  int bpc;  // workgroups per compute unit the grid is sized for
+};
+
+struct kc_handle {
+  int device = 0;
+  int n_cu = 256;
+  size_t lds_per_block = 65536;
+  std::string err;
+  void *scratch = nullptr;
+  size_t scratch_bytes = 0;
+  std::string tune_path;
+  std::map<std::string, kc_tile> tune;  // shape bucket -> chosen tile
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+kc_status kc_fail(kc_handle *h, kc_status st, const char *fmt, ...);
+// Returns at least `bytes` of device scratch owned by the handle. Growing the
+// buffer synchronises the device first (work in flight may still use it).
+kc_status kc_get_scratch(kc_handle *h, size_t bytes, void **p);
+// Maps hipGetLastError after a launch to KC_EDEVICE.
+kc_status kc_check_launch(kc_handle *h, const char *what);
+
+// Margin thresholds (float32 values compared against float32 distances).
+// For a float32 squared distance v_hat of exact value v:
+//   v_hat > thr_gt(T)   implies v > T,
+//   v_hat < thr_lt(T)   implies v < T,
+//   v <= T              implies v_hat <= thr_gt(T).
+float kc_thr_gt(double T, int d);
+float kc_thr_lt(double T, int d);
+// Rigorous float64 bounds from a float32 value: lower (never negative) / upper.
+double kc_lower_from_f32(float v, int d);
+double kc_upper_from_f32(float v, int d);
+
+kc_status kc_validate_points(kc_handle *h, const kc_points *p);
+kc_status kc_validate_nodes(kc_handle *h, const kc_nodes *m, const kc_points *p);
+kc_status kc_validate_refs(kc_handle *h, const kc_refs *r, const kc_nodes *m);
+
+// Bound-kernel launch (implemented in kc_bound.hip); `t` selects the variant.
+// mode 0: lower bound (optionally with candidates), mode 1: float32 objective.
+kc_status kc_launch_bound(kc_handle *h, const kc_points *pts, int mode, int n_nodes,
+                          int n_boxes, int k_max, const int32_t *box_off, const float *lo,
+                          const float *hi, float *val_raw, double *val_bound, int64_t *argmax,
+                          int64_t *cand, const kc_tile &t, hipStream_t st);
+// Variants compiled for this (d, with_cand) pair.
+std::vector<kc_tile> kc_bound_variants(int d, bool with_cand, int k_max);
+kc_tile kc_default_tile(kc_handle *h, int d, bool with_cand, int n_nodes, int k_max, int64_t n);
+std::string kc_tune_key(int d, bool with_cand, int n_nodes, int k_max, int64_t n);
+void kc_tune_load(kc_handle *h);
+void kc_tune_save(kc_handle *h);
+
+#define KC_RETURN_IF(cond, h, st, ...)          \
+  do {                                          \
+    if (cond) return kc_fail(h, st, __VA_ARGS__); \
+  } while (0)

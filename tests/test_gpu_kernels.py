@@ -1,0 +1,299 @@
+"""GPU parity: every libkc kernel against the fp64 CPU oracle on identical
+seeded inputs, element by element.
+
+Float32 results must lie within the forward-error margin of the oracle's value
+(gamma_{d+3} relative plus the underflow term); rigorous outputs must bound it
+from the safe side. Indices and masks must be identical except where the
+oracle itself shows that the decision sits inside the margin band (the oracle
+evaluated at the band's two ends disagrees), where the device may take either
+side -- those cases are counted, and must be rare.
+"""
+import numpy as np
+import pytest
+import torch
+
+import datagen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def kc():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2301_00061_amd import api
+    return api
+
+
+def _g(kc, d):
+    return kc.rel_margin(d), kc.abs_margin(d)
+
+
+def _beta_all(X, lo, hi):
+    """Per-sample min over boxes of the box distance, fp64 -- used only to find
+    near-ties of the oracle's own maximum."""
+    c = np.clip(X[:, None, :], lo[None], hi[None])
+    return ((X[:, None, :] - c) ** 2).sum(-1).min(1)
+
+
+LB_CASES = [
+    # n, d, nodes, k, ragged, seed
+    (1, 2, 1, 3, False, 0),
+    (1000, 2, 1, 3, False, 1),
+    (5003, 3, 7, 10, True, 2),
+    (20011, 4, 33, 5, False, 3),
+    (4099, 5, 16, 8, True, 4),
+    (3001, 1, 5, 2, False, 5),
+    (2049, 9, 3, 4, False, 6),
+    (1500, 16, 2, 3, False, 7),
+    (777, 2, 3, 40, True, 8),
+    (70000, 3, 256, 10, False, 9),
+]
+
+
+@pytest.mark.parametrize("n,d,nn,k,ragged,seed", LB_CASES)
+@pytest.mark.parametrize("want_cand", [False, True])
+def test_lower_bound_parity(kc, n, d, nn, k, ragged, seed, want_cand):
+    X = datagen.gaussian_mixture(n, d, 3, 0.1, seed)
+    off, lo, hi = datagen.random_boxes(nn, k, d, seed, wmin=0.01, wmax=0.8, ragged=ragged)
+    X64, lo64, hi64 = X.astype(np.float64), lo.astype(np.float64), hi.astype(np.float64)
+    lb, am = oracle.lower_bound(X64, off, lo64, hi64)
+    xd = kc.to_device_soa(X)
+    lb_raw, lb_safe, am_g, cand_g = kc.lower_bound(
+        xd, n, torch.from_numpy(off).cuda(), torch.from_numpy(lo).cuda(),
+        torch.from_numpy(hi).cuda(), want_cand=want_cand)
+    lb_raw, lb_safe, am_g = lb_raw.cpu().numpy(), lb_safe.cpu().numpy(), am_g.cpu().numpy()
+    g, eta = _g(kc, d)
+    assert np.all(np.abs(lb_raw - lb) <= g * lb + eta)
+    assert np.all(lb_safe <= lb)
+    assert np.all(lb_safe >= lb * (1 - 3 * g) - 2 * eta)
+    ties = 0
+    for m in range(nn):
+        b0, b1 = off[m], off[m + 1]
+        beta = _beta_all(X64, lo64[b0:b1], hi64[b0:b1])
+        band = 2 * (g * lb[m] + eta)
+        near = np.nonzero(beta >= lb[m] - band)[0]
+        if len(near) == 1:
+            assert am_g[m] == am[m]
+        else:
+            ties += 1
+            assert am_g[m] in near
+    assert ties <= max(1, nn // 10)
+    if want_cand:
+        cand = oracle.candidates(X64, lo64, hi64)
+        cand_g = cand_g.cpu().numpy()
+        for b in range(lo.shape[0]):
+            inside = np.all((X >= lo[b]) & (X <= hi[b]), 1)
+            if cand[b] < 0:
+                assert cand_g[b] == -1 and not inside.any()
+                continue
+            assert inside[cand_g[b]]
+            mid = 0.5 * (lo64[b] + hi64[b])
+            dist = ((X64 - mid) ** 2).sum(1)
+            dist[~inside] = np.inf
+            dmin = dist[cand[b]]
+            tol = 2 * g * dmin + 1e-6 * (1 + np.sqrt(dmin)) * max(1.0, np.abs(mid).max())
+            assert dist[cand_g[b]] <= dmin + tol
+
+
+def test_lower_bound_exact_ties_take_lowest_index(kc):
+    rng = np.random.default_rng(0)
+    base = rng.uniform(0, 1, (50, 2)).astype(np.float32)
+    X = np.concatenate([base, base, base])  # every value appears three times
+    perm = rng.permutation(len(X))
+    X = X[perm]
+    off = np.array([0, 2], dtype=np.int32)
+    lo = np.array([[0.1, 0.1], [0.6, 0.6]], dtype=np.float32)
+    hi = np.array([[0.2, 0.3], [0.7, 0.65]], dtype=np.float32)
+    lb, am = oracle.lower_bound(X.astype(np.float64), off, lo.astype(np.float64), hi.astype(np.float64))
+    xd = kc.to_device_soa(X)
+    _, _, am_g, cand_g = kc.lower_bound(xd, len(X), torch.from_numpy(off).cuda(),
+                                        torch.from_numpy(lo).cuda(), torch.from_numpy(hi).cuda(),
+                                        want_cand=True)
+    assert am_g.item() == am[0]
+    cand = oracle.candidates(X.astype(np.float64), lo.astype(np.float64), hi.astype(np.float64))
+    assert cand_g.cpu().tolist() == cand.tolist()
+
+
+def test_lower_bound_is_deterministic(kc):
+    X = datagen.gaussian_mixture(300000, 3, 3, 0.1, 11)
+    off, lo, hi = datagen.random_boxes(64, 10, 3, 11, wmin=0.01, wmax=0.5)
+    xd = kc.to_device_soa(X)
+    args = (torch.from_numpy(off).cuda(), torch.from_numpy(lo).cuda(), torch.from_numpy(hi).cuda())
+    r1 = kc.lower_bound(xd, len(X), *args, want_cand=True)
+    r2 = kc.lower_bound(xd, len(X), *args, want_cand=True)
+    for a, b in zip(r1, r2):
+        assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("n,d,ns,k,seed", [(1, 2, 1, 1, 0), (4097, 2, 3, 3, 1), (30011, 4, 9, 5, 2),
+                                           (10000, 5, 40, 8, 3), (2000, 11, 2, 4, 4)])
+def test_objective_parity(kc, n, d, ns, k, seed):
+    X = datagen.gaussian_mixture(n, d, 3, 0.1, seed)
+    rng = np.random.default_rng(seed)
+    C = np.concatenate([X[rng.integers(0, n, (ns // 2 + 1) * k)].reshape(-1, k, d),
+                        datagen.random_centers(ns, k, d, seed)])[:ns]
+    X64 = X.astype(np.float64)
+    obj, am = oracle.objective(X64, C.astype(np.float64))
+    xd = kc.to_device_soa(X)
+    Cd = torch.from_numpy(np.ascontiguousarray(C)).cuda()
+    # float64: same operations in the same order -> identical values and indices
+    o64, a64 = kc.objective(xd, n, Cd, precision=64)
+    assert np.array_equal(o64.cpu().numpy(), obj)
+    assert np.array_equal(a64.cpu().numpy(), am)
+    # float32 screen: rounded up, never below the exact value
+    o32, a32 = kc.objective(xd, n, Cd, precision=32)
+    o32, a32 = o32.cpu().numpy(), a32.cpu().numpy()
+    g, eta = _g(kc, d)
+    assert np.all(o32 >= obj)
+    assert np.all(o32 <= obj * (1 + 3 * g) + 3 * eta)
+    for c in range(ns):
+        q = ((X64[:, None, :] - C[c].astype(np.float64)[None]) ** 2).sum(-1).min(1)
+        near = np.nonzero(q >= obj[c] - 2 * (g * obj[c] + eta))[0]
+        assert a32[c] in near
+
+
+def _tighten_case(seed, n, d, k, nn=1, with_refs=True, alpha_scale=1.2):
+    X = datagen.gaussian_mixture(n, d, k, 0.08, seed)
+    X64 = X.astype(np.float64)
+    T = oracle.fft(X64, k, seed % n)
+    z, _ = oracle.objective(X64, X64[T][None])
+    alpha = float(z[0]) * alpha_scale
+    rng = np.random.default_rng(seed)
+    los, his = [], []
+    for m in range(nn):
+        c = X[T] + rng.normal(0, 0.05, (k, d)).astype(np.float32)
+        w = rng.uniform(0.02, 0.6, (k, d)).astype(np.float32)
+        los.append(c - w)
+        his.append(c + w)
+    lo = np.concatenate(los).astype(np.float32)
+    hi = np.concatenate(his).astype(np.float32)
+    off = (np.arange(nn + 1) * k).astype(np.int32)
+    if with_refs:
+        ref_off = np.arange(nn * k + 1, dtype=np.int32)
+        ref = np.tile(X[T], (nn, 1)).astype(np.float32)
+    else:
+        ref_off, ref = None, None
+    return X, off, lo, hi, alpha, ref_off, ref
+
+
+@pytest.mark.parametrize("seed,n,d,k,nn,with_refs", [
+    (0, 3000, 2, 3, 1, True), (1, 20000, 2, 3, 1, False), (2, 9001, 3, 5, 1, True),
+    (3, 5000, 4, 5, 6, True), (4, 4000, 5, 8, 3, False), (5, 2500, 2, 10, 4, True),
+    (6, 3000, 10, 3, 2, True), (7, 1, 2, 2, 1, True)])
+def test_tighten_parity(kc, seed, n, d, k, nn, with_refs):
+    X, off, lo, hi, alpha, ref_off, ref = _tighten_case(seed, n, d, k, nn, with_refs)
+    X64 = X.astype(np.float64)
+    g, eta = _g(kc, d)
+    delta = 3 * g + 1e-12
+    xd = kc.to_device_soa(X)
+    dev = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    out = kc.tighten(xd, n, dev(off), dev(lo), dev(hi), alpha, dev(ref_off), dev(ref),
+                     labels=(nn == 1), k_max=k, max_refs=1 if with_refs else None)
+    res = {key: (v.cpu().numpy() if v is not None else None) for key, v in out.items()}
+    unstable_nodes = 0
+    for m in range(nn):
+        sl = slice(off[m], off[m + 1])
+        r_off = None if ref_off is None else (ref_off[off[m]:off[m + 1] + 1] - ref_off[off[m]])
+        r = None if ref is None else ref[ref_off[off[m]]:ref_off[off[m + 1]]].astype(np.float64)
+        runs = [oracle.tighten_node(X64, lo[sl].astype(np.float64), hi[sl].astype(np.float64),
+                                    a, r_off, r, want_labels=True)
+                for a in (alpha, alpha * (1 - delta), alpha * (1 + delta))]
+        o = runs[0]
+        stable = np.ones(n, dtype=bool)
+        for rr in runs[1:]:
+            stable &= rr["labels"] == o["labels"]
+        if nn == 1:
+            lab = res["labels"]
+            assert np.array_equal(lab[stable], o["labels"][stable])
+            assert (~stable).sum() <= max(2, n // 1000)
+        same_aggs = all(np.array_equal(rr[key], o[key]) for rr in runs[1:]
+                        for key in ("bb_lo", "bb_hi", "n_in", "asg_min", "asg_max", "n_asg"))
+        if not (same_aggs and stable.all()):
+            unstable_nodes += 1
+            continue
+        assert res["n_excl"][m] == o["n_excluded"]
+        assert np.array_equal(res["n_in"][sl], o["n_in"])
+        assert np.array_equal(res["n_asg"][sl], o["n_asg"])
+        for key in ("bb_lo", "bb_hi", "asg_min", "asg_max"):
+            assert np.array_equal(res[key][sl].astype(np.float64), o[key]), key
+    assert unstable_nodes <= max(1, nn // 3)
+
+
+@pytest.mark.parametrize("seed,n,d,nn,k", [(0, 10000, 2, 5, 3), (1, 50021, 3, 20, 5),
+                                           (2, 3000, 4, 1, 4), (3, 1025, 2, 3, 2),
+                                           (4, 8000, 12, 4, 3)])
+def test_reduce_parity(kc, seed, n, d, nn, k):
+    X = datagen.gaussian_mixture(n, d, 3, 0.1, seed)
+    X64 = X.astype(np.float64)
+    off, lo, hi = datagen.random_boxes(nn, k, d, seed, wmin=0.05, wmax=0.6)
+    rng = np.random.default_rng(seed)
+    nb = lo.shape[0]
+    ref_off = np.arange(nb + 1, dtype=np.int32)
+    ref = X[rng.integers(0, n, nb)].astype(np.float32)
+    # beta at the median over samples of the worst node's farthest-corner
+    # distance, so that about half of the samples are deletable
+    far = np.stack([np.maximum(np.abs(X64[:, None, :] - lo[off[m]:off[m + 1]][None]),
+                               np.abs(X64[:, None, :] - hi[off[m]:off[m + 1]][None])) ** 2
+                    for m in range(nn)], 0).sum(-1).min(-1).max(0)
+    beta, alpha = float(np.quantile(far, 0.5)), 0.01
+    g, eta = _g(kc, d)
+    delta = 3 * g + 1e-12
+    args = (off, lo.astype(np.float64), hi.astype(np.float64), ref_off, ref.astype(np.float64))
+    keep_o = oracle.reduce_flags(X64, *args, beta, alpha)
+    keep_lo = oracle.reduce_flags(X64, *args, beta * (1 - delta), alpha * (1 + delta))
+    xd = kc.to_device_soa(X)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    idx_in = dev((np.arange(n, dtype=np.uint32) * 7 + 3).view(np.int32))
+    x_out, idx_out, n_out, keep_g = kc.reduce(xd, n, dev(off), dev(lo), dev(hi), beta, alpha,
+                                              dev(ref_off), dev(ref), idx_in=idx_in,
+                                              want_keep=True)
+    keep_g = keep_g.cpu().numpy()
+    stable = keep_o == keep_lo
+    assert np.array_equal(keep_g[stable], keep_o[stable])
+    # the device deletes a subset of what the exact test deletes, and a superset
+    # of what the test moved by the margin deletes
+    assert np.all(keep_g >= keep_o) and np.all(keep_g <= keep_lo)
+    assert (~stable).sum() <= max(2, n // 1000)
+    assert 0 < keep_o.sum() < n or n < 2000
+    m = int(n_out.item())
+    assert m == int(keep_g.sum())
+    sel = np.nonzero(keep_g)[0]
+    xo = x_out.cpu().numpy()[:, :m]
+    assert np.array_equal(xo, X[sel].T)
+    io = idx_out.cpu().numpy()[:m].view(np.uint32)
+    assert np.array_equal(io, (sel * 7 + 3).astype(np.uint32))
+
+
+def test_reduce_without_refs_and_identity_index(kc):
+    X = datagen.gaussian_mixture(5000, 2, 3, 0.1, 9)
+    off = np.array([0, 3], dtype=np.int32)
+    lo = np.array([[0.2, 0.2], [0.5, 0.5], [0.8, 0.1]], dtype=np.float32)
+    hi = lo + np.float32(0.05)
+    beta = 0.02
+    keep_o = oracle.reduce_flags(X.astype(np.float64), off, lo.astype(np.float64),
+                                 hi.astype(np.float64), np.zeros(4, dtype=np.int32),
+                                 np.zeros((1, 2)), beta, 1.0)
+    xd = kc.to_device_soa(X)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    x_out, idx_out, n_out, keep_g = kc.reduce(xd, len(X), dev(off), dev(lo), dev(hi), beta, 1.0,
+                                              want_keep=True)
+    kg = keep_g.cpu().numpy()
+    diff = np.nonzero(kg != keep_o)[0]
+    assert len(diff) <= 2
+    sel = np.nonzero(kg)[0]
+    assert int(n_out.item()) == len(sel)
+    assert np.array_equal(idx_out.cpu().numpy()[:len(sel)], sel)
+
+
+def test_autotune_picks_a_variant_and_keeps_results(kc):
+    X = datagen.uniform_points(200000, 3, 1)
+    off, lo, hi = datagen.random_boxes(32, 10, 3, 1)
+    xd = kc.to_device_soa(X)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    args = (dev(off), dev(lo), dev(hi))
+    before = kc.lower_bound(xd, len(X), *args)
+    ms = kc.autotune(xd, len(X), *args)
+    assert ms > 0
+    after = kc.lower_bound(xd, len(X), *args)
+    assert torch.equal(before[0], after[0]) and torch.equal(before[2], after[2])
