@@ -203,7 +203,7 @@ kc_status kc_mlp_adam(kc_handle *h, float *w32, uint16_t *w_bf16, const float *d
 /* ------------------------------------------------- host driver ----------- */
 
 typedef struct {
-  int32_t k;            /* clusters                                         */
+  int32_t k;            /* clusters, 1..64                                  */
   int32_t batch;        /* nodes popped per pass (>= 1)                     */
   int32_t i_sr;         /* sample reduction every i_sr passes; 0 = off      */
   int32_t use_bt;       /* 1: assignment + tightening (BB+CF+BT)            */
@@ -215,7 +215,16 @@ typedef struct {
   double time_limit_s;  /* 0 = unlimited                                    */
   const uint16_t *mlp_w;/* device bf16 weights for branching = 1, or NULL   */
   int32_t verbose;      /* 1: progress lines on stderr                      */
-  int32_t reserved;
+  /* Strong-branching labels (training data of the branching network): the
+   * first sb_first branched nodes and every sb_every-th after them get every
+   * positive-width candidate (cluster, attribute) split and bounded; one row
+   * per candidate is written to the host arrays below (capacity sb_cap). */
+  int32_t sb_first;
+  int32_t sb_every;     /* 0 = no labels                                    */
+  int32_t sb_cap;
+  float *sb_feat;       /* host [sb_cap][32] candidate features             */
+  float *sb_score;      /* host [sb_cap] product score of the two children  */
+  int32_t *sb_node;     /* host [sb_cap] ordinal of the labelled node       */
 } kc_opts;
 
 typedef struct {
@@ -232,6 +241,8 @@ typedef struct {
   double lb_kernel_ms;  /* total time inside kc_lower_bound launches         */
   int32_t seeds_found;
   int32_t status;       /* 0 closed (gap <= eps_rel), 1 node limit, 2 time limit */
+  int32_t sb_rows;      /* strong-branching rows written                     */
+  int32_t sb_nodes;     /* strong-branching nodes labelled                   */
 } kc_result;
 
 /* Algorithm 1 on the device-resident samples `pts` (synchronous; uses its own

@@ -43,7 +43,8 @@ class Opts(C.Structure):
                 ("use_bt", C.c_int32), ("use_seeds", C.c_int32), ("branching", C.c_int32),
                 ("fft_start", C.c_int64), ("max_nodes", C.c_int64), ("eps_rel", C.c_double),
                 ("time_limit_s", C.c_double), ("mlp_w", C.c_void_p), ("verbose", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("sb_first", C.c_int32), ("sb_every", C.c_int32), ("sb_cap", C.c_int32),
+                ("sb_feat", C.c_void_p), ("sb_score", C.c_void_p), ("sb_node", C.c_void_p)]
 
 
 class Result(C.Structure):
@@ -51,7 +52,8 @@ class Result(C.Structure):
                 ("fft_obj", C.c_double), ("centers", C.c_int64 * 64), ("nodes", C.c_int64),
                 ("passes", C.c_int64), ("evals", C.c_int64), ("n_active", C.c_int64),
                 ("seconds", C.c_double), ("lb_kernel_ms", C.c_double),
-                ("seeds_found", C.c_int32), ("status", C.c_int32)]
+                ("seeds_found", C.c_int32), ("status", C.c_int32), ("sb_rows", C.c_int32),
+                ("sb_nodes", C.c_int32)]
 
 
 _lib = None

@@ -63,14 +63,14 @@ extern "C" double kc_rel_margin(int d) {
 
 extern "C" double kc_abs_margin(int d) { return (double)(d + 3) * 0x1p-126; }
 
-static float round_up_f32(double v) {
+float kc_round_up_f32(double v) {
   if (!(v < (double)FLT_MAX)) return INFINITY;
   float f = (float)v;
   if ((double)f < v) f = nextafterf(f, INFINITY);
   return f;
 }
 
-static float round_down_f32(double v) {
+float kc_round_down_f32(double v) {
   if (!(v > -(double)FLT_MAX)) return -INFINITY;
   float f = (float)v;
   if ((double)f > v) f = nextafterf(f, -INFINITY);
@@ -79,12 +79,12 @@ static float round_down_f32(double v) {
 
 float kc_thr_gt(double T, int d) {
   if (std::isinf(T)) return T > 0 ? INFINITY : -INFINITY;
-  return round_up_f32(T * (1.0 + kc_rel_margin(d) + 0x1p-50) + kc_abs_margin(d));
+  return kc_round_up_f32(T * (1.0 + kc_rel_margin(d) + 0x1p-50) + kc_abs_margin(d));
 }
 
 float kc_thr_lt(double T, int d) {
   if (std::isinf(T)) return T > 0 ? INFINITY : -INFINITY;
-  return round_down_f32(T * (1.0 - kc_rel_margin(d) - 0x1p-50) - kc_abs_margin(d));
+  return kc_round_down_f32(T * (1.0 - kc_rel_margin(d) - 0x1p-50) - kc_abs_margin(d));
 }
 
 double kc_lower_from_f32(float v, int d) {

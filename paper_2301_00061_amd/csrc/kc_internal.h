@@ -45,6 +45,9 @@ kc_status kc_check_launch(kc_handle *h, const char *what);
 //   v <= T              implies v_hat <= thr_gt(T).
 float kc_thr_gt(double T, int d);
 float kc_thr_lt(double T, int d);
+// float32 nearest to v in the stated direction.
+float kc_round_up_f32(double v);
+float kc_round_down_f32(double v);
 // Rigorous float64 bounds from a float32 value: lower (never negative) / upper.
 double kc_lower_from_f32(float v, int d);
 double kc_upper_from_f32(float v, int d);
@@ -65,6 +68,10 @@ kc_tile kc_default_tile(kc_handle *h, int d, bool with_cand, int n_nodes, int k_
 std::string kc_tune_key(int d, bool with_cand, int n_nodes, int k_max, int64_t n);
 void kc_tune_load(kc_handle *h);
 void kc_tune_save(kc_handle *h);
+
+// Device gather of sample coordinates (kc_util.hip).
+kc_status kc_gather(kc_handle *h, const kc_points *p, const int64_t *ids, int count,
+                    const uint32_t *idx_map, float *out, int64_t *orig, hipStream_t st);
 
 #define KC_RETURN_IF(cond, h, st, ...)          \
   do {                                          \

@@ -17,6 +17,3 @@ extern "C" kc_status kc_mlp_adam(kc_handle *h, float *, uint16_t *, const float 
                                  int32_t, float, void *) {
   return kc_fail(h, KC_EUNSUPPORTED, "kc_mlp_adam not built");
 }
-extern "C" kc_status kc_solve(kc_handle *h, const kc_points *, const kc_opts *, kc_result *) {
-  return kc_fail(h, KC_EUNSUPPORTED, "kc_solve not built");
-}

@@ -1,0 +1,959 @@
+// kc_solve.cpp -- host branch and bound (Algorithm 1) over the libkc calls.
+//
+// Per pass: pop up to `batch` open nodes of least lower bound; one kc_tighten
+// launch gives the assignment / tightening aggregates of all of them
+// (Algorithms 3-4) and the host forms the tightened boxes; every `i_sr` passes
+// kc_reduce deletes the samples redundant in every open node (Algorithm 5);
+// each surviving node is split (max-range rule of Section 3.3, or the learned
+// rule) and one kc_lower_bound launch bounds all children and returns their
+// Section 3.2 candidates; one kc_objective launch screens the candidates in
+// float32 (rounded up); an improvement is certified in float64 over the
+// original samples. Nodes are pruned when their rigorous lower bound reaches
+// the incumbent, and every node that leaves the tree records the bound it
+// leaves behind, so the final lower bound is rigorous too.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "kc_internal.h"
+
+// Host float64 arithmetic stays unfused so that distance sums round exactly as
+// written (the seeds test compares them with 4 alpha).
+#pragma clang fp contract(off)
+
+namespace {
+
+constexpr int NFEAT = 32;
+
+struct DevBuf {
+  void *p = nullptr;
+  size_t cap = 0;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  bool ensure(size_t bytes) {
+    if (bytes <= cap) return true;
+    if (p) {
+      (void)hipDeviceSynchronize();
+      (void)hipFree(p);
+      p = nullptr;
+      cap = 0;
+    }
+    const size_t nb = bytes + bytes / 2 + 256;
+    if (hipMalloc(&p, nb) != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+      return false;
+    }
+    cap = nb;
+    return true;
+  }
+  template <class T>
+  T *as() const {
+    return (T *)p;
+  }
+};
+
+struct Node {
+  std::vector<float> lo, hi;     // K*D (row k: lo[k*D + a])
+  double lb = 0.0;               // rigorous lower bound
+  double parent_lb = 0.0;
+  int64_t id = 0;
+  int depth = 0;
+  int split_k = -1, split_a = -1, side = -1;
+  std::vector<uint8_t> nsplit;   // K*D: splits of (k,a) on the path
+  float xstar[16] = {0};         // sample attaining the node's lower bound
+};
+
+struct HeapCmp {
+  bool operator()(const Node *a, const Node *b) const {
+    return a->lb > b->lb || (a->lb == b->lb && a->id > b->id);
+  }
+};
+
+inline double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Splits [lo, hi] (lo < hi) into [lo, m] and [next(m), hi]: together they hold
+// every float32 of [lo, hi], and centers are float32 samples.
+void split_interval(float lo, float hi, float *l_hi, float *r_lo) {
+  float m = kc_round_down_f32(0.5 * ((double)lo + (double)hi));
+  if (m >= hi) m = nextafterf(hi, -INFINITY);
+  if (m < lo) m = lo;
+  *l_hi = m;
+  *r_lo = nextafterf(m, INFINITY);
+}
+
+struct Solver {
+  kc_handle *h;
+  const kc_points *X0;
+  kc_opts o;
+  kc_result *res;
+  int K, D;
+  hipStream_t st = nullptr;
+
+  // active samples
+  kc_points act;
+  const uint32_t *idx = nullptr;  // active -> original (null: identity)
+  DevBuf xbuf[2], ibuf[2];
+  int cur = -1;
+
+  // incumbent
+  double alpha_cert = INFINITY;   // float64 objective over all samples
+  double alpha_ub = INFINITY;     // valid upper bound used for pruning
+  std::vector<int64_t> inc_ids;
+  std::vector<float> inc_coords;
+  double lb_closed = INFINITY;    // least bound among nodes that left the tree
+
+  // root data
+  std::vector<float> root_lo, root_hi;
+  bool seeds = false, symmetry = false;
+  std::vector<float> seed_coords;  // K*D
+
+  std::vector<Node *> heap;
+  int64_t next_id = 0, n_branched = 0;
+  int sb_nodes = 0, sb_rows = 0;
+
+  // pseudocosts per (k,a): sums and counts of relative LB gains
+  std::vector<double> pc_sum[2];
+  std::vector<int> pc_cnt[2];
+
+  // device buffers
+  DevBuf d_off, d_lo, d_hi, d_roff, d_ref;
+  DevBuf d_bblo, d_bbhi, d_nin, d_amin, d_amax, d_nasg, d_nexcl;
+  DevBuf d_lbraw, d_lbsafe, d_argmax, d_cand, d_ids, d_coords, d_orig, d_obj, d_oam;
+  DevBuf d_feat, d_score;
+
+  double t0 = 0;
+
+  Solver(kc_handle *h_, const kc_points *x, const kc_opts *op, kc_result *r)
+      : h(h_), X0(x), o(*op), res(r), K(op->k), D(x->d) {
+    act = *x;
+  }
+  ~Solver() {
+    for (Node *n : heap) delete n;
+    if (st) (void)hipStreamDestroy(st);
+  }
+
+  kc_status sync(const char *what) {
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return kc_fail(h, KC_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+    return KC_OK;
+  }
+  kc_status up(DevBuf &b, const void *src, size_t bytes) {
+    if (!b.ensure(bytes)) return kc_fail(h, KC_ENOMEM, "driver buffer of %zu bytes", bytes);
+    if (bytes && hipMemcpyAsync(b.p, src, bytes, hipMemcpyHostToDevice, st) != hipSuccess)
+      return kc_fail(h, KC_EDEVICE, "upload");
+    return KC_OK;
+  }
+  kc_status down(void *dst, const DevBuf &b, size_t bytes) {
+    if (bytes && hipMemcpyAsync(dst, b.p, bytes, hipMemcpyDeviceToHost, st) != hipSuccess)
+      return kc_fail(h, KC_EDEVICE, "download");
+    return KC_OK;
+  }
+  kc_status alloc(DevBuf &b, size_t bytes) {
+    if (!b.ensure(bytes)) return kc_fail(h, KC_ENOMEM, "driver buffer of %zu bytes", bytes);
+    return KC_OK;
+  }
+
+  double prune_thr() const { return alpha_ub * (1.0 - o.eps_rel); }
+
+  void heap_push(Node *n) {
+    heap.push_back(n);
+    std::push_heap(heap.begin(), heap.end(), HeapCmp());
+  }
+  Node *heap_pop() {
+    std::pop_heap(heap.begin(), heap.end(), HeapCmp());
+    Node *n = heap.back();
+    heap.pop_back();
+    return n;
+  }
+  double global_lb() const {
+    double lb = lb_closed;
+    if (!heap.empty()) lb = std::min(lb, heap.front()->lb);
+    return std::min(lb, alpha_cert);
+  }
+
+  // ---------------------------------------------------------------- root --
+  kc_status root() {
+    // Root region M0 (Section 2.1) as the bounding box of one all-space box.
+    std::vector<float> lo(D, -INFINITY), hi(D, INFINITY);
+    int32_t off[2] = {0, 1};
+    kc_status s = up(d_off, off, sizeof(off));
+    if (s) return s;
+    if ((s = up(d_lo, lo.data(), D * 4)) || (s = up(d_hi, hi.data(), D * 4))) return s;
+    if ((s = alloc(d_bblo, D * 4)) || (s = alloc(d_bbhi, D * 4)) || (s = alloc(d_nin, 4)) ||
+        (s = alloc(d_amin, D * 4)) || (s = alloc(d_amax, D * 4)) || (s = alloc(d_nasg, 4)) ||
+        (s = alloc(d_nexcl, 4)))
+      return s;
+    kc_nodes nd{1, 1, 1, 0, d_off.as<int32_t>(), d_lo.as<float>(), d_hi.as<float>()};
+    s = kc_tighten(h, &act, &nd, INFINITY, nullptr, d_bblo.as<float>(), d_bbhi.as<float>(),
+                   d_nin.as<uint32_t>(), d_amin.as<float>(), d_amax.as<float>(),
+                   d_nasg.as<uint32_t>(), d_nexcl.as<uint32_t>(), nullptr, st);
+    if (s) return s;
+    res->passes++;
+    std::vector<float> bl(D), bh(D);
+    if ((s = down(bl.data(), d_bblo, D * 4)) || (s = down(bh.data(), d_bbhi, D * 4)) ||
+        (s = sync("root box")))
+      return s;
+    root_lo.assign(K * D, 0.f);
+    root_hi.assign(K * D, 0.f);
+    for (int k = 0; k < K; ++k)
+      for (int a = 0; a < D; ++a) {
+        root_lo[k * D + a] = bl[a];
+        root_hi[k * D + a] = bh[a];
+      }
+
+    // Farthest first traversal (Algorithm 2), distances in float64.
+    std::vector<int64_t> T(K);
+    T[0] = o.fft_start;
+    if ((s = alloc(d_ids, 64 * 8)) || (s = alloc(d_coords, 64 * D * 4)) ||
+        (s = alloc(d_orig, 64 * 8)) || (s = alloc(d_obj, 8)) || (s = alloc(d_oam, 8)))
+      return s;
+    for (int j = 1; j <= K; ++j) {
+      if ((s = up(d_ids, T.data(), j * 8))) return s;
+      if ((s = kc_gather(h, &act, d_ids.as<int64_t>(), j, nullptr, d_coords.as<float>(), nullptr, st)))
+        return s;
+      s = kc_objective(h, &act, 1, j, d_coords.as<float>(), 64, d_obj.as<double>(),
+                       d_oam.as<int64_t>(), st);
+      if (s) return s;
+      res->passes++;
+      double ob;
+      int64_t am;
+      if ((s = down(&ob, d_obj, 8)) || (s = down(&am, d_oam, 8)) || (s = sync("fft"))) return s;
+      if (j < K)
+        T[j] = am;
+      else
+        alpha_cert = ob;
+    }
+    inc_ids = T;
+    inc_coords.resize(K * D);
+    if ((s = down(inc_coords.data(), d_coords, K * D * 4)) || (s = sync("fft centers"))) return s;
+    alpha_ub = alpha_cert;
+    res->fft_obj = alpha_cert;
+
+    // K farthest initial seeds (Section 4.1.1): pairwise farther than 4 alpha.
+    seeds = false;
+    if (o.use_seeds && o.use_bt && K > 1) {
+      seeds = true;
+      for (int i = 0; i < K && seeds; ++i)
+        for (int j = i + 1; j < K; ++j) {
+          double dd = 0;
+          for (int a = 0; a < D; ++a) {
+            const double t = (double)inc_coords[i * D + a] - (double)inc_coords[j * D + a];
+            dd += t * t;
+          }
+          if (!(dd > 4.0 * alpha_cert)) {
+            seeds = false;
+            break;
+          }
+        }
+    }
+    if (seeds) seed_coords = inc_coords;
+    symmetry = !seeds && o.use_bt;
+    res->seeds_found = seeds;
+
+    Node *r = new Node();
+    r->lo = root_lo;
+    r->hi = root_hi;
+    r->lb = 0.0;
+    r->id = next_id++;
+    r->nsplit.assign(K * D, 0);
+    if (symmetry) apply_symmetry(r->lo, r->hi);
+    heap_push(r);
+    for (int s2 = 0; s2 < 2; ++s2) {
+      pc_sum[s2].assign(K * D, 0.0);
+      pc_cnt[s2].assign(K * D, 0);
+    }
+    return KC_OK;
+  }
+
+  // Section 4.1.3: mu_1^1 <= ... <= mu_1^K on the first attribute.
+  bool apply_symmetry(std::vector<float> &lo, std::vector<float> &hi) const {
+    for (int k = 1; k < K; ++k) lo[k * D] = std::max(lo[k * D], lo[(k - 1) * D]);
+    for (int k = K - 2; k >= 0; --k) hi[k * D] = std::min(hi[k * D], hi[(k + 1) * D]);
+    for (int k = 0; k < K; ++k)
+      if (lo[k * D] > hi[k * D]) return false;
+    return true;
+  }
+
+  kc_status upload_nodes(const std::vector<const std::vector<float> *> &los,
+                         const std::vector<const std::vector<float> *> &his, kc_nodes *nd,
+                         kc_refs *rf, bool with_refs) {
+    const int nn = (int)los.size();
+    std::vector<int32_t> off(nn + 1);
+    std::vector<float> lo((size_t)nn * K * D), hi((size_t)nn * K * D);
+    for (int i = 0; i < nn; ++i) {
+      off[i] = i * K;
+      std::memcpy(&lo[(size_t)i * K * D], los[i]->data(), K * D * 4);
+      std::memcpy(&hi[(size_t)i * K * D], his[i]->data(), K * D * 4);
+    }
+    off[nn] = nn * K;
+    kc_status s;
+    if ((s = up(d_off, off.data(), off.size() * 4)) || (s = up(d_lo, lo.data(), lo.size() * 4)) ||
+        (s = up(d_hi, hi.data(), hi.size() * 4)))
+      return s;
+    *nd = kc_nodes{nn, nn * K, K, 0, d_off.as<int32_t>(), d_lo.as<float>(), d_hi.as<float>()};
+    if (with_refs) {
+      std::vector<int32_t> roff(nn * K + 1);
+      std::vector<float> ref((size_t)nn * K * D);
+      for (int b = 0; b < nn * K; ++b) {
+        roff[b] = b;
+        std::memcpy(&ref[(size_t)b * D], &seed_coords[(b % K) * D], D * 4);
+      }
+      roff[nn * K] = nn * K;
+      if ((s = up(d_roff, roff.data(), roff.size() * 4)) || (s = up(d_ref, ref.data(), ref.size() * 4)))
+        return s;
+      *rf = kc_refs{nn * K, 1, d_roff.as<int32_t>(), d_ref.as<float>()};
+    }
+    return KC_OK;
+  }
+
+  // ------------------------------------------------------------ tighten --
+  // Returns, per node, whether it survived, and replaces its boxes by M-hat.
+  struct TAgg {
+    std::vector<float> bbl, bbh, amn, amx;
+    std::vector<uint32_t> nin, nasg, nex;
+  } ta;
+
+  kc_status tighten(std::vector<Node *> &batch, std::vector<char> &alive, double a_bt) {
+    const int nn = (int)batch.size();
+    std::vector<const std::vector<float> *> los(nn), his(nn);
+    for (int i = 0; i < nn; ++i) {
+      los[i] = &batch[i]->lo;
+      his[i] = &batch[i]->hi;
+    }
+    kc_nodes nd;
+    kc_refs rf;
+    const bool wr = seeds && o.use_bt;
+    kc_status s = upload_nodes(los, his, &nd, &rf, wr);
+    if (s) return s;
+    const size_t nbd = (size_t)nn * K * D, nb = (size_t)nn * K;
+    if ((s = alloc(d_bblo, nbd * 4)) || (s = alloc(d_bbhi, nbd * 4)) || (s = alloc(d_amin, nbd * 4)) ||
+        (s = alloc(d_amax, nbd * 4)) || (s = alloc(d_nin, nb * 4)) || (s = alloc(d_nasg, nb * 4)) ||
+        (s = alloc(d_nexcl, nn * 4)))
+      return s;
+    s = kc_tighten(h, &act, &nd, a_bt, wr ? &rf : nullptr, d_bblo.as<float>(), d_bbhi.as<float>(),
+                   d_nin.as<uint32_t>(), d_amin.as<float>(), d_amax.as<float>(),
+                   d_nasg.as<uint32_t>(), d_nexcl.as<uint32_t>(), nullptr, st);
+    if (s) return s;
+    res->passes++;
+    ta.bbl.resize(nbd);
+    ta.bbh.resize(nbd);
+    ta.amn.resize(nbd);
+    ta.amx.resize(nbd);
+    ta.nin.resize(nb);
+    ta.nasg.resize(nb);
+    ta.nex.resize(nn);
+    if ((s = down(ta.bbl.data(), d_bblo, nbd * 4)) || (s = down(ta.bbh.data(), d_bbhi, nbd * 4)) ||
+        (s = down(ta.amn.data(), d_amin, nbd * 4)) || (s = down(ta.amx.data(), d_amax, nbd * 4)) ||
+        (s = down(ta.nin.data(), d_nin, nb * 4)) || (s = down(ta.nasg.data(), d_nasg, nb * 4)) ||
+        (s = down(ta.nex.data(), d_nexcl, nn * 4)) || (s = sync("tighten")))
+      return s;
+
+    const double sa = o.use_bt ? std::sqrt(a_bt) * (1.0 + 0x1p-50) : INFINITY;
+    alive.assign(nn, 1);
+    for (int i = 0; i < nn; ++i) {
+      Node *m = batch[i];
+      bool ok = ta.nex[i] == 0;
+      for (int k = 0; k < K && ok; ++k) {
+        const size_t b = (size_t)i * K + k;
+        if (ta.nin[b] == 0) {
+          ok = false;
+          break;
+        }
+        for (int a = 0; a < D; ++a) {
+          const size_t q = b * D + a;
+          float L = std::max(m->lo[k * D + a], ta.bbl[q]);
+          float H = std::min(m->hi[k * D + a], ta.bbh[q]);
+          if (o.use_bt && std::isfinite(sa)) {
+            // box-based tightening with the assigned samples and the seed
+            double amax = -INFINITY, amin = INFINITY;
+            if (ta.nasg[b] > 0) {
+              amax = ta.amx[q];
+              amin = ta.amn[q];
+            }
+            if (seeds) {
+              amax = std::max(amax, (double)seed_coords[k * D + a]);
+              amin = std::min(amin, (double)seed_coords[k * D + a]);
+            }
+            if (std::isfinite(amax)) {
+              const double v = nextafter(amax - sa, -INFINITY);
+              L = std::max(L, kc_round_up_f32(v));
+            }
+            if (std::isfinite(amin)) {
+              const double v = nextafter(amin + sa, INFINITY);
+              H = std::min(H, kc_round_down_f32(v));
+            }
+          }
+          if (!(L <= H)) ok = false;
+          m->lo[k * D + a] = L;
+          m->hi[k * D + a] = H;
+        }
+      }
+      if (ok && symmetry) ok = apply_symmetry(m->lo, m->hi);
+      // an infeasible node holds no solution of objective <= a_bt
+      alive[i] = ok;
+    }
+    return KC_OK;
+  }
+
+  // ---------------------------------------------------- sample reduction --
+  kc_status reduce(const std::vector<Node *> &extra) {
+    std::vector<const std::vector<float> *> los, his;
+    double beta = INFINITY;
+    const double thr = prune_thr();
+    for (Node *m : heap)
+      if (m->lb < thr) {
+        los.push_back(&m->lo);
+        his.push_back(&m->hi);
+        beta = std::min(beta, m->lb);
+      }
+    for (Node *m : extra) {
+      los.push_back(&m->lo);
+      his.push_back(&m->hi);
+      beta = std::min(beta, m->lb);
+    }
+    if (los.empty()) return KC_OK;
+    kc_nodes nd;
+    kc_refs rf;
+    const bool wr = seeds && o.use_bt;
+    kc_status s = upload_nodes(los, his, &nd, &rf, wr);
+    if (s) return s;
+    const int nxt = cur == 0 ? 1 : 0;
+    const size_t bytes = (size_t)D * X0->ld * 4;
+    if (!xbuf[nxt].ensure(bytes) || !ibuf[nxt].ensure((size_t)X0->ld * 4))
+      return kc_fail(h, KC_ENOMEM, "sample buffers");
+    if ((s = alloc(d_obj, 8))) return s;
+    s = kc_reduce(h, &act, idx, &nd, wr ? &rf : nullptr, beta, alpha_ub, nullptr,
+                  xbuf[nxt].as<float>(), ibuf[nxt].as<uint32_t>(), X0->ld, d_obj.as<int64_t>(), st);
+    if (s) return s;
+    res->passes++;
+    int64_t n_out = 0;
+    if ((s = down(&n_out, d_obj, 8)) || (s = sync("reduce"))) return s;
+    if (n_out < 1) return KC_OK;  // keep the previous set (nothing left to bound)
+    cur = nxt;
+    act.x = xbuf[cur].as<float>();
+    act.n = n_out;
+    act.ld = X0->ld;
+    idx = ibuf[cur].as<uint32_t>();
+    return KC_OK;
+  }
+
+  // ------------------------------------------------------------ features --
+  // 32 features of candidate (k,a) of node m (tightened boxes), see the
+  // branching network's documentation.
+  void features(const Node *m, int bi, int nbatch, const uint32_t *nin, const uint32_t *nasg,
+                int k, int a, float *f) const {
+    const double al = alpha_ub > 0 ? alpha_ub : 1.0;
+    const double glb = global_lb();
+    double wmax = 0.0;
+    for (int q = 0; q < K * D; ++q) wmax = std::max(wmax, (double)m->hi[q] - m->lo[q]);
+    const double w = (double)m->hi[k * D + a] - m->lo[k * D + a];
+    const double rw = std::max(1e-30, (double)root_hi[a] - root_lo[a]);
+    int rank = 0;
+    for (int q = 0; q < K * D; ++q)
+      if ((double)m->hi[q] - m->lo[q] > w) ++rank;
+    double logvol = 0.0;
+    for (int b = 0; b < D; ++b) {
+      const double rb = std::max(1e-30, (double)root_hi[b] - root_lo[b]);
+      logvol += std::log(((double)m->hi[k * D + b] - m->lo[k * D + b]) / rb + 1e-12);
+    }
+    // distance of the LB sample to every box
+    int nearest = 0;
+    double dk = 0.0, dbest = INFINITY;
+    for (int kk = 0; kk < K; ++kk) {
+      double s = 0;
+      for (int b = 0; b < D; ++b) {
+        const double x = m->xstar[b];
+        const double c = std::min(std::max(x, (double)m->lo[kk * D + b]), (double)m->hi[kk * D + b]);
+        s += (x - c) * (x - c);
+      }
+      if (s < dbest) {
+        dbest = s;
+        nearest = kk;
+      }
+      if (kk == k) dk = s;
+    }
+    const double lo = m->lo[k * D + a], hi = m->hi[k * D + a];
+    const double xs = m->xstar[a];
+    double pos = w > 0 ? (xs - lo) / w : 0.5;
+    pos = std::min(2.0, std::max(-1.0, pos));
+    double overlap = 0.0, mind = INFINITY;
+    for (int kk = 0; kk < K; ++kk) {
+      if (kk == k) continue;
+      const double l2 = m->lo[kk * D + a], h2 = m->hi[kk * D + a];
+      overlap += std::max(0.0, std::min(hi, h2) - std::max(lo, l2));
+      double s = 0;
+      for (int b = 0; b < D; ++b) {
+        const double c1 = 0.5 * ((double)m->lo[k * D + b] + m->hi[k * D + b]);
+        const double c2 = 0.5 * ((double)m->lo[kk * D + b] + m->hi[kk * D + b]);
+        s += (c1 - c2) * (c1 - c2);
+      }
+      mind = std::min(mind, std::sqrt(s));
+    }
+    const double nact = (double)act.n, n0 = (double)X0->n;
+    const int q = k * D + a;
+    const double mean_l = pc_cnt[0][q] ? pc_sum[0][q] / pc_cnt[0][q] : 0.0;
+    const double mean_r = pc_cnt[1][q] ? pc_sum[1][q] / pc_cnt[1][q] : 0.0;
+    int nref = seeds ? K : 0;
+    f[0] = (float)(m->depth / 32.0);
+    f[1] = (float)(std::log1p((double)heap.size()) / 10.0);
+    f[2] = (float)std::min(2.0, m->lb / al);
+    f[3] = (float)std::max(-1.0, (alpha_ub - m->lb) / al);
+    f[4] = (float)std::max(-1.0, (alpha_ub - glb) / al);
+    f[5] = (float)((m->lb - m->parent_lb) / al);
+    f[6] = (float)(K / 16.0);
+    f[7] = (float)(D / 16.0);
+    f[8] = (float)(nact / n0);
+    f[9] = seeds ? 1.f : 0.f;
+    f[10] = (float)((double)nref / K);
+    f[11] = (float)((double)bi / std::max(1, nbatch));
+    f[12] = (float)(w / rw);
+    f[13] = (float)(wmax > 0 ? w / wmax : 0.0);
+    f[14] = (float)((double)rank / (K * D));
+    f[15] = (float)(logvol / D / 10.0);
+    f[16] = (float)(std::log1p((double)nin[k]) / std::log1p(n0));
+    f[17] = (float)(std::log1p((double)nasg[k]) / std::log1p(n0));
+    f[18] = nearest == k ? 1.f : 0.f;
+    f[19] = (float)std::min(4.0, dk / al);
+    f[20] = (float)pos;
+    f[21] = (xs < lo || xs > hi) ? 1.f : 0.f;
+    f[22] = (float)((0.5 * (lo + hi) - root_lo[a]) / rw);
+    f[23] = (float)(w > 0 ? std::min(8.0, overlap / w) : 0.0);
+    f[24] = (float)(std::isfinite(mind) ? std::min(8.0, mind / std::sqrt(al)) : 8.0);
+    f[25] = (float)((double)m->nsplit[q] / (m->depth + 1));
+    f[26] = (float)std::max(-1.0, std::min(4.0, mean_l));
+    f[27] = (float)std::max(-1.0, std::min(4.0, mean_r));
+    f[28] = (float)(std::log1p((double)pc_cnt[0][q]) / 10.0);
+    f[29] = (float)(std::log1p((double)pc_cnt[1][q]) / 10.0);
+    f[30] = (float)((0.5 * (lo + hi) - root_lo[a]) / rw - 0.5);
+    f[31] = 0.f;
+  }
+
+  // Picks (k,a) for every node to branch. Max-range rule (Section 3.3):
+  // widest box side, lowest k then a on ties; learned rule: highest network
+  // score among positive-width candidates, max-range when the network is off.
+  kc_status choose(const std::vector<Node *> &nodes, const std::vector<int> &bidx,
+                   std::vector<int> &ck, std::vector<int> &ca) {
+    const int nn = (int)nodes.size();
+    ck.assign(nn, -1);
+    ca.assign(nn, -1);
+    for (int i = 0; i < nn; ++i) {
+      const Node *m = nodes[i];
+      double bw = 0.0;
+      for (int k = 0; k < K; ++k)
+        for (int a = 0; a < D; ++a) {
+          const double w = (double)m->hi[k * D + a] - m->lo[k * D + a];
+          if (w > bw) {
+            bw = w;
+            ck[i] = k;
+            ca[i] = a;
+          }
+        }
+    }
+    if (o.branching != 1 || !o.mlp_w) return KC_OK;
+    std::vector<float> feat;
+    std::vector<int> row_node, row_q;
+    for (int i = 0; i < nn; ++i) {
+      const Node *m = nodes[i];
+      for (int k = 0; k < K; ++k)
+        for (int a = 0; a < D; ++a) {
+          if (!((double)m->hi[k * D + a] - m->lo[k * D + a] > 0)) continue;
+          feat.resize(feat.size() + NFEAT);
+          features(m, bidx[i], (int)nodes.size(), &ta.nin[(size_t)bidx[i] * K],
+                   &ta.nasg[(size_t)bidx[i] * K], k, a, &feat[feat.size() - NFEAT]);
+          row_node.push_back(i);
+          row_q.push_back(k * D + a);
+        }
+    }
+    const int64_t rows = (int64_t)row_node.size();
+    if (rows == 0) return KC_OK;
+    kc_status s;
+    if ((s = up(d_feat, feat.data(), feat.size() * 4)) || (s = alloc(d_score, rows * 4))) return s;
+    s = kc_mlp_forward(h, o.mlp_w, d_feat.as<float>(), rows, d_score.as<float>(), nullptr, st);
+    if (s) return s;
+    std::vector<float> sc(rows);
+    if ((s = down(sc.data(), d_score, rows * 4)) || (s = sync("branching network"))) return s;
+    std::vector<float> best(nn, -INFINITY);
+    for (int64_t r = 0; r < rows; ++r) {
+      const int i = row_node[r];
+      if (sc[r] > best[i]) {  // first (lowest (k,a)) wins ties
+        best[i] = sc[r];
+        ck[i] = row_q[r] / D;
+        ca[i] = row_q[r] % D;
+      }
+    }
+    return KC_OK;
+  }
+
+  // Strong branching at labelled nodes: every positive-width (k,a) is split,
+  // both children bounded in one launch; score = max(dL, e) * max(dR, e).
+  kc_status strong_branching(const std::vector<Node *> &nodes, const std::vector<int> &bidx) {
+    std::vector<std::vector<float>> clo, chi;
+    struct Cand {
+      int node, k, a;
+    };
+    std::vector<Cand> cands;
+    for (int i = 0; i < (int)nodes.size(); ++i) {
+      const Node *m = nodes[i];
+      for (int k = 0; k < K; ++k)
+        for (int a = 0; a < D; ++a) {
+          const float l = m->lo[k * D + a], hh = m->hi[k * D + a];
+          if (!(l < hh)) continue;
+          float lh, rl;
+          split_interval(l, hh, &lh, &rl);
+          std::vector<float> L1 = m->lo, H1 = m->hi, L2 = m->lo, H2 = m->hi;
+          H1[k * D + a] = lh;
+          L2[k * D + a] = rl;
+          clo.push_back(L1);
+          chi.push_back(H1);
+          clo.push_back(L2);
+          chi.push_back(H2);
+          cands.push_back({i, k, a});
+        }
+    }
+    if (cands.empty()) return KC_OK;
+    std::vector<const std::vector<float> *> los, his;
+    for (size_t c = 0; c < clo.size(); ++c) {
+      los.push_back(&clo[c]);
+      his.push_back(&chi[c]);
+    }
+    kc_nodes nd;
+    kc_refs rf;
+    kc_status s = upload_nodes(los, his, &nd, &rf, false);
+    if (s) return s;
+    const int ne = (int)los.size();
+    if ((s = alloc(d_lbsafe, ne * 8)) || (s = alloc(d_cand, (size_t)ne * K * 8))) return s;
+    s = kc_lower_bound(h, &act, &nd, nullptr, d_lbsafe.as<double>(), nullptr, d_cand.as<int64_t>(), st);
+    if (s) return s;
+    std::vector<double> lb(ne);
+    std::vector<int64_t> cand((size_t)ne * K);
+    if ((s = down(lb.data(), d_lbsafe, ne * 8)) || (s = down(cand.data(), d_cand, cand.size() * 8)) ||
+        (s = sync("strong branching")))
+      return s;
+    const double al = alpha_ub;
+    const double e = 1e-6 * al;
+    int last = -1;
+    for (size_t c = 0; c < cands.size(); ++c) {
+      const Node *m = nodes[cands[c].node];
+      double g[2];
+      for (int side = 0; side < 2; ++side) {
+        const int j = (int)(2 * c + side);
+        bool empty = false;
+        for (int k = 0; k < K; ++k)
+          if (cand[(size_t)j * K + k] < 0) empty = true;
+        const double clb = empty ? al : std::min(al, std::max(m->lb, lb[j]));
+        g[side] = std::max(clb - m->lb, e);
+      }
+      if (sb_rows >= o.sb_cap) break;
+      if (cands[c].node != last) {
+        last = cands[c].node;
+        ++sb_nodes;
+      }
+      features(m, bidx[cands[c].node], (int)nodes.size(), &ta.nin[(size_t)bidx[cands[c].node] * K],
+               &ta.nasg[(size_t)bidx[cands[c].node] * K], cands[c].k, cands[c].a,
+               &o.sb_feat[(size_t)sb_rows * NFEAT]);
+      o.sb_score[sb_rows] = (float)(g[0] * g[1] / (al * al));
+      o.sb_node[sb_rows] = sb_nodes - 1;
+      ++sb_rows;
+    }
+    return KC_OK;
+  }
+
+  // --------------------------------------------------------------- run --
+  kc_status run() {
+    t0 = now_s();
+    if (hipStreamCreate(&st) != hipSuccess) return kc_fail(h, KC_EDEVICE, "stream");
+    kc_status s = root();
+    if (s) return s;
+    int64_t passes_since_sr = 0;
+    res->status = 0;
+    std::vector<Node *> batch;
+    std::vector<char> alive;
+    while (!heap.empty()) {
+      if (o.max_nodes > 0 && res->nodes >= o.max_nodes) {
+        res->status = 1;
+        break;
+      }
+      if (o.time_limit_s > 0 && now_s() - t0 > o.time_limit_s) {
+        res->status = 2;
+        break;
+      }
+      // node selection: least lower bound first
+      batch.clear();
+      const double thr = prune_thr();
+      while ((int)batch.size() < o.batch && !heap.empty()) {
+        Node *m = heap_pop();
+        if (m->lb >= thr) {
+          lb_closed = std::min(lb_closed, m->lb);
+          delete m;
+          continue;
+        }
+        batch.push_back(m);
+      }
+      if (batch.empty()) break;
+      res->nodes += (int64_t)batch.size();
+
+      // bounds tightening
+      const double a_bt = o.use_bt ? alpha_ub : INFINITY;
+      if ((s = tighten(batch, alive, a_bt))) return s;
+      std::vector<Node *> live;
+      std::vector<int> bidx;
+      for (size_t i = 0; i < batch.size(); ++i) {
+        if (alive[i]) {
+          live.push_back(batch[i]);
+          bidx.push_back((int)i);
+        } else {
+          lb_closed = std::min(lb_closed, std::max(batch[i]->lb, a_bt));
+          delete batch[i];
+        }
+      }
+      // sample reduction every i_sr passes, over the open nodes and this batch
+      ++passes_since_sr;
+      if (o.i_sr > 0 && passes_since_sr >= o.i_sr) {
+        passes_since_sr = 0;
+        if ((s = reduce(live))) return s;
+      }
+
+      // branching; a node whose boxes are all single points is a leaf
+      std::vector<Node *> to_branch, leaves;
+      std::vector<int> to_branch_bidx;
+      for (size_t i = 0; i < live.size(); ++i) {
+        Node *m = live[i];
+        bool leaf = true;
+        for (int q = 0; q < K * D; ++q)
+          if (m->lo[q] != m->hi[q]) leaf = false;
+        if (leaf)
+          leaves.push_back(m);
+        else {
+          to_branch.push_back(m);
+          to_branch_bidx.push_back(bidx[i]);
+        }
+      }
+      std::vector<int> ck, ca;
+      if ((s = choose(to_branch, to_branch_bidx, ck, ca))) return s;
+      if (o.sb_every > 0 && o.sb_feat && o.sb_score && o.sb_node) {
+        std::vector<Node *> lab;
+        std::vector<int> lab_b;
+        for (size_t i = 0; i < to_branch.size(); ++i) {
+          const int64_t ord = n_branched + (int64_t)i;
+          if (ord < o.sb_first || (ord - o.sb_first) % o.sb_every == 0) {
+            lab.push_back(to_branch[i]);
+            lab_b.push_back(to_branch_bidx[i]);
+          }
+        }
+        if (!lab.empty() && sb_rows < o.sb_cap)
+          if ((s = strong_branching(lab, lab_b))) return s;
+      }
+      n_branched += (int64_t)to_branch.size();
+
+      // children (and leaves) to bound
+      std::vector<Node *> ev;
+      std::vector<char> is_leaf;
+      for (size_t i = 0; i < to_branch.size(); ++i) {
+        Node *m = to_branch[i];
+        const int k = ck[i], a = ca[i];
+        float lh, rl;
+        split_interval(m->lo[k * D + a], m->hi[k * D + a], &lh, &rl);
+        for (int side = 0; side < 2; ++side) {
+          Node *c = new Node();
+          c->lo = m->lo;
+          c->hi = m->hi;
+          if (side == 0)
+            c->hi[k * D + a] = lh;
+          else
+            c->lo[k * D + a] = rl;
+          c->parent_lb = m->lb;
+          c->lb = m->lb;
+          c->depth = m->depth + 1;
+          c->split_k = k;
+          c->split_a = a;
+          c->side = side;
+          c->nsplit = m->nsplit;
+          if (c->nsplit[k * D + a] < 255) c->nsplit[k * D + a]++;
+          c->id = next_id++;
+          if (symmetry && !apply_symmetry(c->lo, c->hi)) {
+            delete c;  // empty box: no solution
+            continue;
+          }
+          ev.push_back(c);
+          is_leaf.push_back(0);
+        }
+        delete m;
+      }
+      for (Node *m : leaves) {
+        ev.push_back(m);
+        is_leaf.push_back(1);
+      }
+      if (!ev.empty())
+        if ((s = bound(ev, is_leaf))) return s;
+
+      if (!heap.empty()) {
+        const double lb = global_lb();
+        if (alpha_cert - lb <= o.eps_rel * alpha_cert) break;
+      }
+      if (o.verbose && (res->nodes % (o.batch * 20) < o.batch))
+        fprintf(stderr, "[kc_solve] nodes %lld open %zu n_active %lld alpha %.9g lb %.9g t %.2fs\n",
+                (long long)res->nodes, heap.size(), (long long)act.n, alpha_cert, global_lb(),
+                now_s() - t0);
+    }
+    return KC_OK;
+  }
+
+  // Bounds every node of `ev`: lower bound + candidates in one launch, the
+  // candidates' objective in one float32 launch, float64 certificate of an
+  // improvement. Children with an empty box are dropped; leaves leave the tree.
+  kc_status bound(std::vector<Node *> &ev, const std::vector<char> &is_leaf) {
+    const int ne = (int)ev.size();
+    std::vector<const std::vector<float> *> los(ne), his(ne);
+    for (int i = 0; i < ne; ++i) {
+      los[i] = &ev[i]->lo;
+      his[i] = &ev[i]->hi;
+    }
+    kc_nodes nd;
+    kc_refs rf;
+    kc_status s = upload_nodes(los, his, &nd, &rf, false);
+    if (s) return s;
+    if ((s = alloc(d_lbraw, ne * 4)) || (s = alloc(d_lbsafe, ne * 8)) || (s = alloc(d_argmax, ne * 8)) ||
+        (s = alloc(d_cand, (size_t)ne * K * 8)))
+      return s;
+    (void)hipEventRecord(h->ev0, st);
+    s = kc_lower_bound(h, &act, &nd, d_lbraw.as<float>(), d_lbsafe.as<double>(), d_argmax.as<int64_t>(),
+                       d_cand.as<int64_t>(), st);
+    (void)hipEventRecord(h->ev1, st);
+    if (s) return s;
+    res->passes++;
+    res->evals += act.n * (int64_t)ne * K;
+    std::vector<double> lb(ne);
+    std::vector<int64_t> am(ne), cand((size_t)ne * K);
+    if ((s = down(lb.data(), d_lbsafe, ne * 8)) || (s = down(am.data(), d_argmax, ne * 8)) ||
+        (s = down(cand.data(), d_cand, cand.size() * 8)) || (s = sync("lower bound")))
+      return s;
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, h->ev0, h->ev1);
+    res->lb_kernel_ms += ms;
+
+    // candidate sets of the nodes whose boxes all hold a sample
+    std::vector<int> keep;
+    std::vector<int64_t> ids;
+    for (int i = 0; i < ne; ++i) {
+      bool empty = false;
+      for (int k = 0; k < K; ++k)
+        if (cand[(size_t)i * K + k] < 0) empty = true;
+      if (empty) {
+        // no sample in some box: the node holds no feasible centers
+        delete ev[i];
+        ev[i] = nullptr;
+        continue;
+      }
+      keep.push_back(i);
+      for (int k = 0; k < K; ++k) ids.push_back(cand[(size_t)i * K + k]);
+    }
+    const int C = (int)keep.size();
+    for (int i : keep) ids.push_back(am[i]);  // LB samples, for the features
+    const int ng = (int)ids.size();
+    if (C == 0) return KC_OK;
+    if ((s = up(d_ids, ids.data(), ids.size() * 8)) || (s = alloc(d_coords, (size_t)ng * D * 4)) ||
+        (s = alloc(d_orig, (size_t)ng * 8)) || (s = alloc(d_obj, (size_t)C * 8)) ||
+        (s = alloc(d_oam, (size_t)C * 8)))
+      return s;
+    if ((s = kc_gather(h, &act, d_ids.as<int64_t>(), ng, idx, d_coords.as<float>(), d_orig.as<int64_t>(), st)))
+      return s;
+    s = kc_objective(h, &act, C, K, d_coords.as<float>(), 32, d_obj.as<double>(), d_oam.as<int64_t>(), st);
+    if (s) return s;
+    res->passes++;
+    std::vector<double> ub(C);
+    std::vector<float> coords((size_t)ng * D);
+    std::vector<int64_t> orig(ng);
+    if ((s = down(ub.data(), d_obj, C * 8)) || (s = down(coords.data(), d_coords, coords.size() * 4)) ||
+        (s = down(orig.data(), d_orig, orig.size() * 8)) || (s = sync("objective")))
+      return s;
+    int best = -1;
+    for (int c = 0; c < C; ++c)
+      if (ub[c] < alpha_ub && (best < 0 || ub[c] < ub[best])) best = c;
+    if (best >= 0) {
+      alpha_ub = ub[best];
+      // certify in float64 over the original samples
+      if ((s = kc_objective(h, X0, 1, K, d_coords.as<float>() + (size_t)best * K * D, 64,
+                            d_obj.as<double>(), d_oam.as<int64_t>(), st)))
+        return s;
+      res->passes++;
+      double cert;
+      if ((s = down(&cert, d_obj, 8)) || (s = sync("certificate"))) return s;
+      if (cert < alpha_cert) {
+        alpha_cert = cert;
+        inc_ids.assign(orig.begin() + (size_t)best * K, orig.begin() + (size_t)best * K + K);
+        inc_coords.assign(coords.begin() + (size_t)best * K * D, coords.begin() + (size_t)best * K * D + K * D);
+      }
+      alpha_ub = std::min(alpha_ub, alpha_cert);
+    }
+    const double thr = prune_thr();
+    const int d = D;
+    for (int c = 0; c < C; ++c) {
+      const int i = keep[c];
+      Node *m = ev[i];
+      m->lb = std::max(m->lb, lb[i]);
+      for (int a = 0; a < D; ++a) m->xstar[a] = coords[((size_t)C * K + c) * D + a];
+      if (!is_leaf[i] && m->split_k >= 0) {
+        const int q = m->split_k * D + m->split_a;
+        pc_sum[m->side][q] += (m->lb - m->parent_lb) / (alpha_ub > 0 ? alpha_ub : 1.0);
+        pc_cnt[m->side][q]++;
+      }
+      if (is_leaf[i]) {
+        // every box is one point: the node's only solution has objective ub[c]
+        const double lo_obj = std::max(0.0, (ub[c] - kc_abs_margin(d)) / (1.0 + kc_rel_margin(d) + 0x1p-50) *
+                                                (1.0 - kc_rel_margin(d) - 0x1p-50) - kc_abs_margin(d));
+        lb_closed = std::min(lb_closed, std::max(m->lb, lo_obj));
+        delete m;
+      } else if (m->lb >= thr) {
+        lb_closed = std::min(lb_closed, m->lb);
+        delete m;
+      } else {
+        heap_push(m);
+      }
+      ev[i] = nullptr;
+    }
+    return KC_OK;
+  }
+};
+
+}  // namespace
+
+extern "C" kc_status kc_solve(kc_handle *h, const kc_points *pts, const kc_opts *opts,
+                              kc_result *res) {
+  if (!h) return KC_EINVAL;
+  kc_status s = kc_validate_points(h, pts);
+  if (s != KC_OK) return s;
+  KC_RETURN_IF(!opts || !res, h, KC_EINVAL, "opts / result is NULL");
+  KC_RETURN_IF(opts->k < 1 || opts->k > 64 || opts->k > pts->n, h, KC_EINVAL,
+               "k must be in [1, min(64, n)] (got %d)", opts->k);
+  KC_RETURN_IF(opts->batch < 1, h, KC_EINVAL, "batch must be >= 1");
+  KC_RETURN_IF(opts->fft_start < 0 || opts->fft_start >= pts->n, h, KC_EINVAL,
+               "fft_start out of range");
+  KC_RETURN_IF(!(opts->eps_rel >= 0.0 && opts->eps_rel < 1.0), h, KC_EINVAL, "eps_rel in [0,1)");
+  KC_RETURN_IF(opts->branching == 1 && !opts->mlp_w, h, KC_EINVAL, "learned branching needs mlp_w");
+  std::memset(res, 0, sizeof(*res));
+  Solver S(h, pts, opts, res);
+  const double t0 = now_s();
+  s = S.run();
+  if (s != KC_OK) {
+    (void)hipDeviceSynchronize();
+    return s;
+  }
+  res->obj = S.alpha_cert;
+  res->lb = S.global_lb();
+  res->gap = S.alpha_cert > 0 ? (S.alpha_cert - res->lb) / S.alpha_cert : 0.0;
+  for (int k = 0; k < opts->k; ++k) res->centers[k] = S.inc_ids[k];
+  res->n_active = S.act.n;
+  res->sb_rows = S.sb_rows;
+  res->sb_nodes = S.sb_nodes;
+  res->seconds = now_s() - t0;
+  return KC_OK;
+}

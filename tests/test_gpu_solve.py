@@ -1,0 +1,118 @@
+"""GPU end-to-end: the device branch and bound (kc_solve) reaches the optimum
+the fp64 oracle and brute force find, within 1e-6 relative, with a rigorous
+lower bound and centers that attain the certified objective."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import datagen
+import oracle
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def kc():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2301_00061_amd import api
+    return api
+
+
+def _check(X64, r, opt):
+    assert abs(r["obj"] - opt) <= 1e-6 * opt, (r["obj"], opt)
+    assert r["lb"] <= opt * (1 + 1e-12) + 1e-300
+    assert r["obj"] >= opt
+    assert r["gap"] <= 1e-6 + 1e-12
+    obj, _ = oracle.objective(X64, X64[r["centers"]][None])
+    assert obj[0] == r["obj"]
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_solve_small_mixture(kc, seed):
+    X = datagen.small_mixture(seed)
+    X64 = X.astype(np.float64)
+    ro = oracle.solve(X64, 3)
+    r = kc.solve(kc.to_device_soa(X), len(X), 3, batch=16, i_sr=4)
+    assert r["status"] == 0
+    _check(X64, r, ro["obj"])
+    assert r["fft_obj"] == ro["fft_obj"]
+    assert r["seeds_found"] == ro["seeds_found"]
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_solve_slice_vs_brute_force(kc, seed):
+    X = datagen.small_mixture(seed)[:30]
+    X64 = X.astype(np.float64)
+    for k in (2, 3, 4):
+        best, _ = oracle.brute_force(X64, k)
+        r = kc.solve(kc.to_device_soa(X), 30, k, batch=8, i_sr=2)
+        _check(X64, r, best)
+
+
+def test_solve_hand_instances(kc):
+    with open(os.path.join(GOLDEN, "hand_instances.json")) as f:
+        cases = json.load(f)["cases"]
+    for case in cases:
+        X = np.array(case["points"], dtype=np.float32)
+        for ks, want in case["opt"].items():
+            k = int(ks)
+            r = kc.solve(kc.to_device_soa(X), len(X), k, batch=4, i_sr=1)
+            if want == 0:
+                assert r["obj"] == 0.0
+            else:
+                _check(X.astype(np.float64), r, float(want))
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_solve_k1_k2_full_size(kc, k):
+    X = datagen.small_mixture(7)
+    X64 = X.astype(np.float64)
+    best = oracle.solve(X64, k)["obj"]
+    r = kc.solve(kc.to_device_soa(X), len(X), k, batch=32)
+    _check(X64, r, best)
+
+
+def test_solve_one_dimensional(kc):
+    X = datagen.gaussian_mixture(20000, 1, 3, 0.05, 3)
+    X64 = X.astype(np.float64)
+    ro = oracle.solve(X64, 3)
+    r = kc.solve(kc.to_device_soa(X), len(X), 3, batch=32)
+    _check(X64, r, ro["obj"])
+
+
+@pytest.mark.parametrize("opts", [dict(use_bt=False, i_sr=0), dict(i_sr=0), dict(use_seeds=False),
+                                  dict(batch=1), dict(batch=256, i_sr=1)])
+def test_solve_variants_agree(kc, opts):
+    X = datagen.small_mixture(2)
+    X64 = X.astype(np.float64)
+    opt = oracle.solve(X64, 3)["obj"]
+    kw = dict(batch=16, i_sr=4)
+    kw.update(opts)
+    r = kc.solve(kc.to_device_soa(X), len(X), 3, **kw)
+    _check(X64, r, opt)
+
+
+def test_solve_node_limit_keeps_valid_bounds(kc):
+    X = datagen.small_mixture(1)
+    X64 = X.astype(np.float64)
+    opt = oracle.solve(X64, 3)["obj"]
+    r = kc.solve(kc.to_device_soa(X), len(X), 3, batch=4, max_nodes=8)
+    assert r["status"] == 1
+    assert r["lb"] <= opt <= r["obj"]
+    obj, _ = oracle.objective(X64, X64[r["centers"]][None])
+    assert obj[0] == r["obj"]
+
+
+def test_solve_rejects_bad_arguments(kc):
+    X = datagen.small_mixture(0)
+    xd = kc.to_device_soa(X)
+    with pytest.raises(kc.KCError):
+        kc.solve(xd, len(X), 0)
+    with pytest.raises(kc.KCError):
+        kc.solve(xd, len(X), 3, fft_start=len(X))
+    with pytest.raises(kc.KCError):
+        kc.solve(xd, len(X), 3, batch=0)
