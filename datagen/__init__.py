@@ -185,3 +185,58 @@ def mlp_init_weights(seed: int) -> np.ndarray:
         parts.append(rng.uniform(-lim, lim, o * i))
         parts.append(np.zeros(o))
     return np.concatenate(parts).astype(np.float32)
+
+
+def gaussian_mixture_device(n: int, d: int, k: int, std: float, seed: int,
+                            outlier_frac: float = 0.0, outlier_lo: float = -0.5,
+                            outlier_hi: float = 1.5, device="cuda", ld: int | None = None):
+    """Device-side generator for the large workloads (10^7..10^9 samples).
+
+    Same family as ``gaussian_mixture`` (means from the same seed, i.i.d.
+    categorical labels, float64 draws rounded once to float32) but drawn with
+    torch's seeded device generator straight into the structure-of-arrays
+    layout ``[d, ld]`` (padding zeroed). It is a different stream from the host
+    generator: parity checks on these sizes copy the samples they need back to
+    the host. Returns the float32 tensor ``[d, ld]``.
+    """
+    import torch
+    n = int(n)
+    if ld is None:
+        ld = (n + 63) // 64 * 64
+    means = torch.from_numpy(_means(seed, k, d)).to(device)  # [k, d] float64
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed) * 1000003 + 17)
+    x = torch.zeros((d, ld), dtype=torch.float32, device=device)
+    n_out = int(round(n * outlier_frac))
+    n_in = n - n_out
+    step = 1 << 25
+    for a0 in range(0, n_in, step):
+        m = min(step, n_in - a0)
+        lab = torch.randint(0, k, (m,), generator=g, device=device)
+        z = torch.randn((d, m), generator=g, device=device, dtype=torch.float64)
+        x[:, a0:a0 + m] = (means[lab].T + std * z).to(torch.float32)
+    for a0 in range(n_in, n, step):
+        m = min(step, n - a0)
+        u = torch.rand((d, m), generator=g, device=device, dtype=torch.float64)
+        x[:, a0:a0 + m] = (outlier_lo + (outlier_hi - outlier_lo) * u).to(torch.float32)
+    if n_out > 0:
+        perm = torch.randperm(n, generator=g, device=device)
+        for a in range(d):
+            x[a, :n] = x[a, :n][perm]
+    return x
+
+
+def uniform_points_device(n: int, d: int, seed: int, device="cuda", ld: int | None = None):
+    """Device-side ``n`` points uniform in [0,1]^d, layout ``[d, ld]``."""
+    import torch
+    n = int(n)
+    if ld is None:
+        ld = (n + 63) // 64 * 64
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed) * 1000003 + 29)
+    x = torch.zeros((d, ld), dtype=torch.float32, device=device)
+    step = 1 << 25
+    for a0 in range(0, n, step):
+        m = min(step, n - a0)
+        x[:, a0:a0 + m] = torch.rand((d, m), generator=g, device=device, dtype=torch.float64).to(torch.float32)
+    return x

@@ -141,6 +141,10 @@ kc_status kc_objective(kc_handle *h, const kc_points *pts, int32_t n_sets, int32
  *   asg_min, asg_max, n_asg  min / max / count of samples assigned to b
  * per node: n_excl[m]   samples excluded from every box (the node then lies
  *                       above alpha and may be dropped).
+ * asg_far (nullable, [n_boxes]): per box the assigned sample farthest from the
+ *   box midpoint (float32 midpoint and distance; lowest index among equal
+ *   distances), -1 if none -- a sample known to belong to the box's cluster,
+ *   usable as a ref by the node's descendants.
  * labels (nullable, [n], only with n_nodes == 1): assigned box within the
  *   node, -1 unassigned, -2 excluded from every box.
  * Tests use thresholds moved by the margin, so assignments are a subset and
@@ -148,7 +152,7 @@ kc_status kc_objective(kc_handle *h, const kc_points *pts, int32_t n_sets, int32
 kc_status kc_tighten(kc_handle *h, const kc_points *pts, const kc_nodes *nodes, double alpha,
                      const kc_refs *refs, float *bb_lo, float *bb_hi, uint32_t *n_in,
                      float *asg_min, float *asg_max, uint32_t *n_asg, uint32_t *n_excl,
-                     int8_t *labels, void *stream);
+                     int64_t *asg_far, int8_t *labels, void *stream);
 
 /* Algorithm 5 (Sections 4.2.1-4.2.2) over the open nodes:
  *   LB-redundant in M: min_k max_{mu in M^k} ||x_s - mu||^2 < beta
@@ -208,7 +212,12 @@ typedef struct {
   int32_t i_sr;         /* sample reduction every i_sr passes; 0 = off      */
   int32_t use_bt;       /* 1: assignment + tightening (BB+CF+BT)            */
   int32_t use_seeds;    /* 1: K farthest initial seeds when FFT finds them  */
+  int32_t max_refs;     /* refs kept per cluster and node: the seeds plus the
+                           samples assigned at the node's ancestors (the
+                           farthest from its box midpoint per cluster and
+                           node); 0 = seeds only                            */
   int32_t branching;    /* 0: max-range rule; 1: learned (needs mlp_w)      */
+  int32_t reserved0;
   int64_t fft_start;    /* first FFT sample                                 */
   int64_t max_nodes;    /* 0 = unlimited                                    */
   double eps_rel;       /* relative gap at which to stop (>= 1e-6 advised)  */

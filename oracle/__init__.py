@@ -54,7 +54,7 @@ def lib():
         L.kco_objective.argtypes = [pd, i64, C.c_int, i32, C.c_int, pd, pd, pi64]
         L.kco_tighten_node.restype = i64
         L.kco_tighten_node.argtypes = [pd, i64, C.c_int, C.c_int, pd, pd, d64, pi32, pd,
-                                       pd, pd, pi64, pd, pd, pi64, P(C.c_int8)]
+                                       pd, pd, pi64, pd, pd, pi64, pi64, P(C.c_int8)]
         L.kco_tightened_box.restype = C.c_int
         L.kco_tightened_box.argtypes = [C.c_int, C.c_int, pd, pd, d64, pi32, pd, pd, pd, pi64,
                                         pd, pd, pi64, pd, pd]
@@ -72,7 +72,7 @@ def lib():
 
 class Opts(C.Structure):
     _fields_ = [("k", C.c_int32), ("i_sr", C.c_int32), ("use_bt", C.c_int32),
-                ("use_seeds", C.c_int32), ("fft_start", C.c_int64),
+                ("use_seeds", C.c_int32), ("max_refs", C.c_int32), ("fft_start", C.c_int64),
                 ("max_nodes", C.c_int64), ("eps", C.c_double)]
 
 
@@ -161,13 +161,14 @@ def tighten_node(X, lo, hi, alpha, ref_off=None, ref=None, want_labels=False):
     amn, amx = np.zeros((k, d)), np.zeros((k, d))
     nin, nasg = np.zeros(k, dtype=np.int64), np.zeros(k, dtype=np.int64)
     labels = np.zeros(n, dtype=np.int8) if want_labels else None
+    far = np.zeros(k, dtype=np.int64)
     n_ex = lib().kco_tighten_node(
         _p(X, C.c_double), n, d, k, _p(lo, C.c_double), _p(hi, C.c_double), float(alpha),
         _p(ref_off, C.c_int32), _p(ref, C.c_double), _p(bbl, C.c_double), _p(bbh, C.c_double),
         _p(nin, C.c_int64), _p(amn, C.c_double), _p(amx, C.c_double), _p(nasg, C.c_int64),
-        _p(labels, C.c_int8) if labels is not None else None)
+        _p(far, C.c_int64), _p(labels, C.c_int8) if labels is not None else None)
     return dict(bb_lo=bbl, bb_hi=bbh, n_in=nin, asg_min=amn, asg_max=amx, n_asg=nasg,
-                n_excluded=int(n_ex), labels=labels)
+                asg_far=far, n_excluded=int(n_ex), labels=labels)
 
 
 def tightened_box(lo, hi, alpha, agg, ref_off=None, ref=None):
@@ -226,11 +227,12 @@ def brute_force(X, k):
     return float(best[0]), ids
 
 
-def solve(X, k, i_sr=10, use_bt=True, use_seeds=True, fft_start=0, max_nodes=0, eps=0.0):
+def solve(X, k, i_sr=10, use_bt=True, use_seeds=True, max_refs=50, fft_start=0, max_nodes=0,
+          eps=0.0):
     """Algorithm 1 to the global optimum; returns a dict of the result."""
     X, n, d = _pts(X)
-    o = Opts(k=k, i_sr=i_sr, use_bt=int(use_bt), use_seeds=int(use_seeds), fft_start=int(fft_start),
-             max_nodes=int(max_nodes), eps=float(eps))
+    o = Opts(k=k, i_sr=i_sr, use_bt=int(use_bt), use_seeds=int(use_seeds), max_refs=int(max_refs),
+             fft_start=int(fft_start), max_nodes=int(max_nodes), eps=float(eps))
     r = Result()
     rc = lib().kco_solve(_p(X, C.c_double), n, d, C.byref(o), C.byref(r))
     if rc != 0:

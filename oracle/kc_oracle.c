@@ -133,14 +133,17 @@ int64_t kco_tighten_node(const double *X, int64_t n, int d, int k,
                          const int32_t *ref_off, const double *ref,
                          double *bb_lo, double *bb_hi, int64_t *n_in,
                          double *asg_min, double *asg_max, int64_t *n_asg,
-                         int8_t *labels) {
+                         int64_t *asg_far, int8_t *labels) {
   int64_t n_excluded = 0;
+  double far_d[KCO_MAX_K];
   int all_have_refs = 1;
   for (int j = 0; j < k; ++j)
     if (ref_off[j + 1] <= ref_off[j]) all_have_refs = 0;
   for (int j = 0; j < k; ++j) {
     n_in[j] = 0;
     n_asg[j] = 0;
+    far_d[j] = -1.0;
+    if (asg_far) asg_far[j] = -1;
     for (int a = 0; a < d; ++a) {
       bb_lo[j * d + a] = INFINITY;
       bb_hi[j * d + a] = -INFINITY;
@@ -193,6 +196,16 @@ int64_t kco_tighten_node(const double *X, int64_t n, int d, int k,
       for (int a = 0; a < d; ++a) {
         if (x[a] < asg_min[label * d + a]) asg_min[label * d + a] = x[a];
         if (x[a] > asg_max[label * d + a]) asg_max[label * d + a] = x[a];
+      }
+      /* the assigned sample farthest from the midpoint of its cluster's box */
+      double dm = 0.0;
+      for (int a = 0; a < d; ++a) {
+        double t = x[a] - 0.5 * (lo[label * d + a] + hi[label * d + a]);
+        dm += t * t;
+      }
+      if (dm > far_d[label]) {
+        far_d[label] = dm;
+        if (asg_far) asg_far[label] = s;
       }
     }
 
@@ -358,10 +371,15 @@ void kco_brute_force(const double *X, int64_t n, int d, int k, double *best, int
 
 /* --------------------------------------------------------- branch and bound */
 
+/* A node: K boxes, its lower bound, and the samples known to belong to each
+ * cluster inside it (refs: the seeds and samples assigned at its ancestors). */
 typedef struct {
   double *lo, *hi; /* k*d each */
   double lb;
   int64_t id;
+  int32_t roff[KCO_MAX_K + 1];
+  double *ref;     /* [roff[k]][d] */
+  int64_t *rid;    /* original ids of the refs */
 } onode;
 
 typedef struct {
@@ -369,7 +387,8 @@ typedef struct {
   int64_t n, cap;
 } oset;
 
-static onode node_new(int k, int d, const double *lo, const double *hi, double lb, int64_t id) {
+static onode node_new(int k, int d, const double *lo, const double *hi, double lb, int64_t id,
+                      const int32_t *roff, const double *ref, const int64_t *rid) {
   onode m;
   m.lo = (double *)malloc(sizeof(double) * k * d);
   m.hi = (double *)malloc(sizeof(double) * k * d);
@@ -377,12 +396,22 @@ static onode node_new(int k, int d, const double *lo, const double *hi, double l
   memcpy(m.hi, hi, sizeof(double) * k * d);
   m.lb = lb;
   m.id = id;
+  memcpy(m.roff, roff, sizeof(int32_t) * (k + 1));
+  int32_t nr = roff[k];
+  m.ref = (double *)malloc(sizeof(double) * (nr > 0 ? nr : 1) * d);
+  m.rid = (int64_t *)malloc(sizeof(int64_t) * (nr > 0 ? nr : 1));
+  if (nr > 0) {
+    memcpy(m.ref, ref, sizeof(double) * nr * d);
+    memcpy(m.rid, rid, sizeof(int64_t) * nr);
+  }
   return m;
 }
 
 static void node_free(onode *m) {
   free(m->lo);
   free(m->hi);
+  free(m->ref);
+  free(m->rid);
 }
 
 static void set_push(oset *S, onode m) {
@@ -416,10 +445,36 @@ static void set_prune(oset *S, double alpha) {
   S->n = w;
 }
 
+/* The children's refs: the parent's refs of each cluster, then the sample the
+ * parent's tightening assigned to the cluster farthest from its box midpoint,
+ * unless already present or the cluster holds max_refs refs. */
+static void child_refs(int k, int d, const onode *M, const int64_t *far, const double *X,
+                       const int64_t *orig, int max_refs, int32_t *roff, double *ref, int64_t *rid) {
+  int32_t w = 0;
+  for (int j = 0; j < k; ++j) {
+    roff[j] = w;
+    for (int32_t r = M->roff[j]; r < M->roff[j + 1]; ++r) {
+      memcpy(ref + (size_t)w * d, M->ref + (size_t)r * d, sizeof(double) * d);
+      rid[w++] = M->rid[r];
+    }
+    if (far && far[j] >= 0 && w - roff[j] < max_refs) {
+      int dup = 0;
+      for (int32_t r = roff[j]; r < w; ++r)
+        if (rid[r] == orig[far[j]]) dup = 1;
+      if (!dup) {
+        memcpy(ref + (size_t)w * d, X + far[j] * d, sizeof(double) * d);
+        rid[w++] = orig[far[j]];
+      }
+    }
+  }
+  roff[k] = w;
+}
+
 int kco_solve(const double *X0, int64_t n0, int d, const kco_opts *opt, kco_result *res) {
   const int k = opt->k;
   if (k < 1 || k > KCO_MAX_K || n0 < k || d < 1 || d > 64) return -1;
   memset(res, 0, sizeof(*res));
+  const int max_refs = opt->max_refs > 0 ? opt->max_refs : 1;
 
   /* The working dataset shrinks under sample reduction; orig maps back. */
   double *X = (double *)malloc(sizeof(double) * (size_t)n0 * d);
@@ -455,7 +510,7 @@ int kco_solve(const double *X0, int64_t n0, int d, const kco_opts *opt, kco_resu
   for (int j = 0; j < k; ++j) res->centers[j] = T[j];
 
   /* K farthest initial seeds (Section 4.1.1): pairwise farther than 4 alpha
-   * means the FFT points lie in distinct clusters; they become the refs. */
+   * means the FFT points lie in distinct clusters; they become the first refs. */
   int seeds = 0;
   if (opt->use_seeds && opt->use_bt && k > 1) {
     seeds = 1;
@@ -464,27 +519,32 @@ int kco_solve(const double *X0, int64_t n0, int d, const kco_opts *opt, kco_resu
         if (!(kco_dist2(X + T[i] * d, X + T[j] * d, d) > 4.0 * alpha)) seeds = 0;
   }
   res->seeds_found = seeds;
-  int32_t *ref_off = (int32_t *)calloc(k + 1, sizeof(int32_t));
-  double *ref = (double *)malloc(sizeof(double) * k * d);
-  if (seeds) {
+  const int grow_refs = opt->use_bt && opt->max_refs > 0;
+  const size_t rcap = (size_t)k * (max_refs + 1);
+  int32_t roff[KCO_MAX_K + 1];
+  double *ref = (double *)malloc(sizeof(double) * rcap * d);
+  int64_t *rid = (int64_t *)malloc(sizeof(int64_t) * rcap);
+  for (int j = 0; j <= k; ++j) roff[j] = seeds ? j : 0;
+  if (seeds)
     for (int j = 0; j < k; ++j) {
       memcpy(ref + j * d, X + T[j] * d, sizeof(double) * d);
-      ref_off[j + 1] = j + 1;
+      rid[j] = T[j];
     }
-  }
   /* Symmetry breaking (Section 4.1.3) only when no seeds were found. */
   const int symmetry = !seeds && opt->use_bt;
 
   oset open = {0};
   int64_t next_id = 0;
-  set_push(&open, node_new(k, d, lo0, hi0, 0.0, next_id++));
+  set_push(&open, node_new(k, d, lo0, hi0, 0.0, next_id++, roff, ref, rid));
 
   double *lo = (double *)malloc(sizeof(double) * k * d), *hi = (double *)malloc(sizeof(double) * k * d);
   double *bbl = (double *)malloc(sizeof(double) * k * d), *bbh = (double *)malloc(sizeof(double) * k * d);
   double *amn = (double *)malloc(sizeof(double) * k * d), *amx = (double *)malloc(sizeof(double) * k * d);
   double *clo = (double *)malloc(sizeof(double) * k * d), *chi = (double *)malloc(sizeof(double) * k * d);
-  int64_t nin[KCO_MAX_K], nasg[KCO_MAX_K], cand[KCO_MAX_K];
+  int64_t nin[KCO_MAX_K], nasg[KCO_MAX_K], cand[KCO_MAX_K], far[KCO_MAX_K];
   int32_t off2[2] = {0, k};
+  int32_t zero_off[KCO_MAX_K + 1];
+  memset(zero_off, 0, sizeof(zero_off));
   int64_t it = 0;
   res->status = 0;
 
@@ -501,17 +561,16 @@ int kco_solve(const double *X0, int64_t n0, int d, const kco_opts *opt, kco_resu
     }
     ++it;
 
-    /* Bounds tightening (Algorithms 3 and 4). Without the acceleration
-     * techniques only the "centers on samples" box is formed (infinite alpha,
-     * no refs), which the finite-termination argument of Section 5 needs. */
+    /* Bounds tightening (Algorithms 3 and 4) with the node's refs. Without the
+     * acceleration techniques only the "centers on samples" box is formed
+     * (infinite alpha, no refs), which the finite-termination argument of
+     * Section 5 needs. */
     double a_bt = opt->use_bt ? alpha : INFINITY;
-    int32_t zero_off[KCO_MAX_K + 1];
-    memset(zero_off, 0, sizeof(zero_off));
-    const int32_t *roff = opt->use_bt ? ref_off : zero_off;
-    int64_t n_ex = kco_tighten_node(X, n, d, k, M.lo, M.hi, a_bt, roff, ref, bbl, bbh, nin, amn, amx,
-                                    nasg, NULL);
-    int infeasible = kco_tightened_box(d, k, M.lo, M.hi, a_bt, roff, ref, bbl, bbh, nin, amn, amx, nasg,
-                                       lo, hi);
+    const int32_t *mroff = opt->use_bt ? M.roff : zero_off;
+    int64_t n_ex = kco_tighten_node(X, n, d, k, M.lo, M.hi, a_bt, mroff, M.ref, bbl, bbh, nin, amn,
+                                    amx, nasg, far, NULL);
+    int infeasible = kco_tightened_box(d, k, M.lo, M.hi, a_bt, mroff, M.ref, bbl, bbh, nin, amn, amx,
+                                       nasg, lo, hi);
     if (!infeasible && symmetry) infeasible = kco_symmetry(d, k, lo, hi);
     if (n_ex > 0 || infeasible) {
       node_free(&M);
@@ -519,33 +578,38 @@ int kco_solve(const double *X0, int64_t n0, int d, const kco_opts *opt, kco_resu
     }
     memcpy(M.lo, lo, sizeof(double) * k * d);
     memcpy(M.hi, hi, sizeof(double) * k * d);
+    /* refs the children inherit (computed before any deletion moves samples) */
+    int32_t croff[KCO_MAX_K + 1];
+    double *cref = (double *)malloc(sizeof(double) * rcap * d);
+    int64_t *crid = (int64_t *)malloc(sizeof(int64_t) * rcap);
+    child_refs(k, d, &M, grow_refs ? far : NULL, X, orig, max_refs, croff, cref, crid);
 
     /* Sample reduction every i_sr iterations (Algorithm 5) over every node:
-     * the open set and the node in hand. */
+     * the open set and the node in hand, each box with its cluster's refs. */
     if (opt->i_sr > 0 && it % opt->i_sr == 0) {
       int32_t nn = (int32_t)open.n + 1;
       int32_t *boff = (int32_t *)malloc(sizeof(int32_t) * (nn + 1));
       double *blo = (double *)malloc(sizeof(double) * (size_t)nn * k * d);
       double *bhi = (double *)malloc(sizeof(double) * (size_t)nn * k * d);
       int32_t *rof = (int32_t *)malloc(sizeof(int32_t) * ((size_t)nn * k + 1));
+      double *rr = (double *)malloc(sizeof(double) * ((size_t)nn * rcap + 1) * d);
       double beta = M.lb;
+      int32_t nr = 0;
+      rof[0] = 0;
       for (int32_t m = 0; m < nn; ++m) {
         const onode *P = m < nn - 1 ? &open.v[m] : &M;
         if (P->lb < beta) beta = P->lb;
         boff[m] = m * k;
         memcpy(blo + (size_t)m * k * d, P->lo, sizeof(double) * k * d);
         memcpy(bhi + (size_t)m * k * d, P->hi, sizeof(double) * k * d);
-      }
-      boff[nn] = nn * k;
-      /* every box j of every node carries the refs of cluster j */
-      rof[0] = 0;
-      double *rr = (double *)malloc(sizeof(double) * ((size_t)nn * k + 1) * d);
-      int32_t nr = 0;
-      for (int32_t m = 0; m < nn; ++m)
         for (int j = 0; j < k; ++j) {
-          for (int32_t r = roff[j]; r < roff[j + 1]; ++r) memcpy(rr + (size_t)(nr++) * d, ref + (size_t)r * d, sizeof(double) * d);
+          if (opt->use_bt)
+            for (int32_t r = P->roff[j]; r < P->roff[j + 1]; ++r)
+              memcpy(rr + (size_t)(nr++) * d, P->ref + (size_t)r * d, sizeof(double) * d);
           rof[m * k + j + 1] = nr;
         }
+      }
+      boff[nn] = nn * k;
       uint8_t *keep = (uint8_t *)malloc((size_t)n);
       kco_reduce_flags(X, n, d, nn, boff, blo, bhi, rof, rr, beta, alpha, keep);
       int64_t w = 0;
@@ -595,6 +659,8 @@ int kco_solve(const double *X0, int64_t n0, int d, const kco_opts *opt, kco_resu
           set_prune(&open, alpha);
         }
       }
+      free(cref);
+      free(crid);
       node_free(&M);
       continue;
     }
@@ -626,8 +692,10 @@ int kco_solve(const double *X0, int64_t n0, int d, const kco_opts *opt, kco_resu
         alpha = ub;
         for (int j = 0; j < k; ++j) res->centers[j] = orig[cand[j]];
       }
-      if (clb < alpha) set_push(&open, node_new(k, d, clo, chi, clb, next_id++));
+      if (clb < alpha) set_push(&open, node_new(k, d, clo, chi, clb, next_id++, croff, cref, crid));
     }
+    free(cref);
+    free(crid);
     set_prune(&open, alpha);
     node_free(&M);
 
@@ -657,7 +725,7 @@ int kco_solve(const double *X0, int64_t n0, int d, const kco_opts *opt, kco_resu
   free(clo);
   free(chi);
   free(ref);
-  free(ref_off);
+  free(rid);
   free(cent);
   free(lo0);
   free(hi0);

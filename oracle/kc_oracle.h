@@ -59,6 +59,8 @@ void kco_objective(const double *X, int64_t n, int d, int32_t n_sets, int k,
  *               every cluster by the center-based test
  *   bb_lo/hi, n_in   bounding box / count of S_+^k = X cap M^k cap balls(refs)
  *   asg_min/max, n_asg   per-cluster min / max / count of assigned samples
+ *   asg_far     (nullable) per cluster the assigned sample farthest from the
+ *               box midpoint (lowest index among equal distances), -1 if none
  * ref_off has k+1 entries (refs of cluster j are rows ref_off[j]..ref_off[j+1]-1).
  * Returns the number of samples excluded from every cluster. */
 int64_t kco_tighten_node(const double *X, int64_t n, int d, int k,
@@ -66,7 +68,7 @@ int64_t kco_tighten_node(const double *X, int64_t n, int d, int k,
                          const int32_t *ref_off, const double *ref,
                          double *bb_lo, double *bb_hi, int64_t *n_in,
                          double *asg_min, double *asg_max, int64_t *n_asg,
-                         int8_t *labels);
+                         int64_t *asg_far, int8_t *labels);
 
 /* Algorithm 4 closing step: the tightened box of every cluster from the
  * aggregates of kco_tighten_node (box-based tightening with the assigned
@@ -104,6 +106,8 @@ typedef struct {
   int32_t use_bt;        /* 1: cluster assignment + ball/box tightening; 0: only
                             the centers-on-samples box */
   int32_t use_seeds;     /* 1: K farthest initial seeds when FFT finds them */
+  int32_t max_refs;      /* refs kept per cluster (seeds + assigned samples
+                            inherited from ancestors); 0 = seeds only */
   int64_t fft_start;     /* first FFT sample */
   int64_t max_nodes;     /* 0 = unlimited */
   double eps;            /* relative gap tolerance; 0 = exact */

@@ -40,8 +40,8 @@ class Refs(C.Structure):
 
 class Opts(C.Structure):
     _fields_ = [("k", C.c_int32), ("batch", C.c_int32), ("i_sr", C.c_int32),
-                ("use_bt", C.c_int32), ("use_seeds", C.c_int32), ("branching", C.c_int32),
-                ("fft_start", C.c_int64), ("max_nodes", C.c_int64), ("eps_rel", C.c_double),
+                ("use_bt", C.c_int32), ("use_seeds", C.c_int32), ("max_refs", C.c_int32),
+                ("branching", C.c_int32), ("reserved0", C.c_int32), ("fft_start", C.c_int64), ("max_nodes", C.c_int64), ("eps_rel", C.c_double),
                 ("time_limit_s", C.c_double), ("mlp_w", C.c_void_p), ("verbose", C.c_int32),
                 ("sb_first", C.c_int32), ("sb_every", C.c_int32), ("sb_cap", C.c_int32),
                 ("sb_feat", C.c_void_p), ("sb_score", C.c_void_p), ("sb_node", C.c_void_p)]
@@ -86,7 +86,7 @@ def load(path: str = LIB_PATH):
     L.kc_objective.argtypes = [vp, P(Points), C.c_int32, C.c_int32, vp, C.c_int32, vp, vp, vp]
     L.kc_tighten.restype = st
     L.kc_tighten.argtypes = [vp, P(Points), P(Nodes), C.c_double, P(Refs), vp, vp, vp, vp, vp,
-                             vp, vp, vp, vp]
+                             vp, vp, vp, vp, vp]
     L.kc_reduce.restype = st
     L.kc_reduce.argtypes = [vp, P(Points), vp, P(Nodes), P(Refs), C.c_double, C.c_double, vp, vp,
                             vp, C.c_int64, vp, vp]

@@ -143,12 +143,14 @@ def tighten(x, n, box_off, lo, hi, alpha, ref_off=None, ref=None, labels=False, 
         asg_max=torch.empty((nb, d), dtype=torch.float32, device=dev),
         n_asg=torch.empty(nb, dtype=torch.int32, device=dev),
         n_excl=torch.empty(M.n_nodes, dtype=torch.int32, device=dev),
+        asg_far=torch.empty(max(1, nb), dtype=torch.int64, device=dev),
         labels=torch.empty(n, dtype=torch.int8, device=dev) if labels else None)
     h.check(h.lib.kc_tighten(h.ptr, C.byref(P), C.byref(M), float(alpha),
                              C.byref(R) if R is not None else None, _ptr(out["bb_lo"]),
                              _ptr(out["bb_hi"]), _ptr(out["n_in"]), _ptr(out["asg_min"]),
                              _ptr(out["asg_max"]), _ptr(out["n_asg"]), _ptr(out["n_excl"]),
-                             _ptr(out["labels"]), _stream()), "kc_tighten")
+                             _ptr(out["asg_far"]), _ptr(out["labels"]), _stream()), "kc_tighten")
+    out["asg_far"] = out["asg_far"][:nb]
     return out
 
 
@@ -221,23 +223,41 @@ def mlp_adam(w32, w_bf16, dw, m, v, step, lr, h: Handle | None = None):
 
 # ---------------------------------------------------------------- driver
 
-def solve(x, n, k, batch=64, i_sr=4, use_bt=True, use_seeds=True, branching=0, fft_start=0,
-          max_nodes=0, eps_rel=1e-6, time_limit_s=0.0, mlp_w=None, verbose=False,
-          h: Handle | None = None) -> dict:
+def solve(x, n, k, batch=64, i_sr=4, use_bt=True, use_seeds=True, max_refs=50, branching=0,
+          fft_start=0, max_nodes=0, eps_rel=1e-6, time_limit_s=0.0, mlp_w=None, verbose=False,
+          sb=None, h: Handle | None = None) -> dict:
     """Algorithm 1 on device-resident samples (synchronous)."""
     h = h or handle()
     P = points(x, n)
     o = Opts(k=k, batch=batch, i_sr=i_sr, use_bt=int(use_bt), use_seeds=int(use_seeds),
-             branching=int(branching), fft_start=int(fft_start), max_nodes=int(max_nodes),
-             eps_rel=float(eps_rel), time_limit_s=float(time_limit_s),
+             max_refs=int(max_refs), branching=int(branching), fft_start=int(fft_start),
+             max_nodes=int(max_nodes), eps_rel=float(eps_rel), time_limit_s=float(time_limit_s),
              mlp_w=mlp_w.data_ptr() if mlp_w is not None else None, verbose=int(verbose))
+    if sb is not None:
+        # strong-branching label recording into host arrays (see StrongBranchingBuffer)
+        o.sb_first, o.sb_every, o.sb_cap = sb.first, sb.every, sb.cap
+        o.sb_feat = sb.feat.ctypes.data
+        o.sb_score = sb.score.ctypes.data
+        o.sb_node = sb.node.ctypes.data
     r = Result()
     torch.cuda.synchronize()
     h.check(h.lib.kc_solve(h.ptr, C.byref(P), C.byref(o), C.byref(r)), "kc_solve")
     return dict(obj=r.obj, lb=r.lb, gap=r.gap, fft_obj=r.fft_obj,
                 centers=np.array(r.centers[:k]), nodes=r.nodes, passes=r.passes, evals=r.evals,
                 n_active=r.n_active, seconds=r.seconds, lb_kernel_ms=r.lb_kernel_ms,
-                seeds_found=bool(r.seeds_found), status=r.status)
+                seeds_found=bool(r.seeds_found), status=r.status, sb_rows=r.sb_rows,
+                sb_nodes=r.sb_nodes)
+
+
+class StrongBranchingBuffer:
+    """Host arrays kc_solve fills with strong-branching rows (features,
+    product score, labelled-node ordinal)."""
+
+    def __init__(self, cap: int, first: int = 32, every: int = 8):
+        self.cap, self.first, self.every = int(cap), int(first), int(every)
+        self.feat = np.zeros((self.cap, 32), dtype=np.float32)
+        self.score = np.zeros(self.cap, dtype=np.float32)
+        self.node = np.zeros(self.cap, dtype=np.int32)
 
 
 def rel_margin(d: int) -> float:

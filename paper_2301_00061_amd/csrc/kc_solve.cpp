@@ -68,6 +68,14 @@ struct Node {
   int split_k = -1, split_a = -1, side = -1;
   std::vector<uint8_t> nsplit;   // K*D: splits of (k,a) on the path
   float xstar[16] = {0};         // sample attaining the node's lower bound
+  // samples known to belong to each cluster inside the node (seeds and the
+  // samples assigned at its ancestors): cluster k owns rows roff[k]..roff[k+1]-1
+  std::vector<int32_t> roff;
+  std::vector<float> ref;        // [rows][D]
+  std::vector<int64_t> rid;      // original sample ids
+  // refs found by this node's tightening, handed to its children
+  std::vector<float> new_ref;    // [K][D]
+  std::vector<int64_t> new_rid;  // [K], -1 = none
 };
 
 struct HeapCmp {
@@ -128,7 +136,7 @@ struct Solver {
   DevBuf d_off, d_lo, d_hi, d_roff, d_ref;
   DevBuf d_bblo, d_bbhi, d_nin, d_amin, d_amax, d_nasg, d_nexcl;
   DevBuf d_lbraw, d_lbsafe, d_argmax, d_cand, d_ids, d_coords, d_orig, d_obj, d_oam;
-  DevBuf d_feat, d_score;
+  DevBuf d_feat, d_score, d_far;
 
   double t0 = 0;
 
@@ -195,7 +203,7 @@ struct Solver {
     kc_nodes nd{1, 1, 1, 0, d_off.as<int32_t>(), d_lo.as<float>(), d_hi.as<float>()};
     s = kc_tighten(h, &act, &nd, INFINITY, nullptr, d_bblo.as<float>(), d_bbhi.as<float>(),
                    d_nin.as<uint32_t>(), d_amin.as<float>(), d_amax.as<float>(),
-                   d_nasg.as<uint32_t>(), d_nexcl.as<uint32_t>(), nullptr, st);
+                   d_nasg.as<uint32_t>(), d_nexcl.as<uint32_t>(), nullptr, nullptr, st);
     if (s) return s;
     res->passes++;
     std::vector<float> bl(D), bh(D);
@@ -265,6 +273,12 @@ struct Solver {
     r->lb = 0.0;
     r->id = next_id++;
     r->nsplit.assign(K * D, 0);
+    r->roff.assign(K + 1, 0);
+    if (seeds) {
+      for (int k = 0; k <= K; ++k) r->roff[k] = k;
+      r->ref = seed_coords;
+      r->rid = inc_ids;
+    }
     if (symmetry) apply_symmetry(r->lo, r->hi);
     heap_push(r);
     for (int s2 = 0; s2 < 2; ++s2) {
@@ -272,6 +286,36 @@ struct Solver {
       pc_cnt[s2].assign(K * D, 0);
     }
     return KC_OK;
+  }
+
+  // A child's refs: its parent's refs of each cluster, then the sample the
+  // parent's tightening assigned to that cluster farthest from the box
+  // midpoint, unless already present or the cluster holds max_refs refs.
+  void inherit_refs(const Node *p, Node *c) const {
+    c->roff.assign(K + 1, 0);
+    c->ref.clear();
+    c->rid.clear();
+    int32_t w = 0;
+    for (int k = 0; k < K; ++k) {
+      c->roff[k] = w;
+      if (!p->roff.empty())
+        for (int r = p->roff[k]; r < p->roff[k + 1]; ++r) {
+          c->ref.insert(c->ref.end(), p->ref.begin() + (size_t)r * D, p->ref.begin() + (size_t)(r + 1) * D);
+          c->rid.push_back(p->rid[r]);
+          ++w;
+        }
+      if (!p->new_rid.empty() && p->new_rid[k] >= 0 && w - c->roff[k] < o.max_refs) {
+        bool dup = false;
+        for (int r = c->roff[k]; r < w; ++r)
+          if (c->rid[r] == p->new_rid[k]) dup = true;
+        if (!dup) {
+          c->ref.insert(c->ref.end(), p->new_ref.begin() + (size_t)k * D, p->new_ref.begin() + (size_t)(k + 1) * D);
+          c->rid.push_back(p->new_rid[k]);
+          ++w;
+        }
+      }
+    }
+    c->roff[K] = w;
   }
 
   // Section 4.1.3: mu_1^1 <= ... <= mu_1^K on the first attribute.
@@ -284,8 +328,7 @@ struct Solver {
   }
 
   kc_status upload_nodes(const std::vector<const std::vector<float> *> &los,
-                         const std::vector<const std::vector<float> *> &his, kc_nodes *nd,
-                         kc_refs *rf, bool with_refs) {
+                         const std::vector<const std::vector<float> *> &his, kc_nodes *nd) {
     const int nn = (int)los.size();
     std::vector<int32_t> off(nn + 1);
     std::vector<float> lo((size_t)nn * K * D), hi((size_t)nn * K * D);
@@ -300,18 +343,34 @@ struct Solver {
         (s = up(d_hi, hi.data(), hi.size() * 4)))
       return s;
     *nd = kc_nodes{nn, nn * K, K, 0, d_off.as<int32_t>(), d_lo.as<float>(), d_hi.as<float>()};
-    if (with_refs) {
-      std::vector<int32_t> roff(nn * K + 1);
-      std::vector<float> ref((size_t)nn * K * D);
-      for (int b = 0; b < nn * K; ++b) {
-        roff[b] = b;
-        std::memcpy(&ref[(size_t)b * D], &seed_coords[(b % K) * D], D * 4);
+    return KC_OK;
+  }
+
+  // Box k of node i gets the refs of cluster k of node i. Returns false (and
+  // uploads nothing) when no node has any ref.
+  kc_status upload_refs(const std::vector<const Node *> &ns, kc_refs *rf, bool *any) {
+    const int nn = (int)ns.size();
+    std::vector<int32_t> roff(nn * K + 1);
+    std::vector<float> ref;
+    int mx = 0;
+    int32_t w = 0;
+    for (int i = 0; i < nn; ++i)
+      for (int k = 0; k < K; ++k) {
+        roff[i * K + k] = w;
+        const Node *m = ns[i];
+        const int c = m->roff.empty() ? 0 : m->roff[k + 1] - m->roff[k];
+        if (c > 0) ref.insert(ref.end(), m->ref.begin() + (size_t)m->roff[k] * D,
+                              m->ref.begin() + (size_t)m->roff[k + 1] * D);
+        w += c;
+        mx = std::max(mx, c);
       }
-      roff[nn * K] = nn * K;
-      if ((s = up(d_roff, roff.data(), roff.size() * 4)) || (s = up(d_ref, ref.data(), ref.size() * 4)))
-        return s;
-      *rf = kc_refs{nn * K, 1, d_roff.as<int32_t>(), d_ref.as<float>()};
-    }
+    roff[nn * K] = w;
+    *any = w > 0;
+    if (!*any) return KC_OK;
+    kc_status s;
+    if ((s = up(d_roff, roff.data(), roff.size() * 4)) || (s = up(d_ref, ref.data(), ref.size() * 4)))
+      return s;
+    *rf = kc_refs{w, mx, d_roff.as<int32_t>(), d_ref.as<float>()};
     return KC_OK;
   }
 
@@ -331,17 +390,22 @@ struct Solver {
     }
     kc_nodes nd;
     kc_refs rf;
-    const bool wr = seeds && o.use_bt;
-    kc_status s = upload_nodes(los, his, &nd, &rf, wr);
+    kc_status s = upload_nodes(los, his, &nd);
     if (s) return s;
+    bool wr = false;
+    if (o.use_bt) {
+      std::vector<const Node *> cn(batch.begin(), batch.end());
+      if ((s = upload_refs(cn, &rf, &wr))) return s;
+    }
     const size_t nbd = (size_t)nn * K * D, nb = (size_t)nn * K;
     if ((s = alloc(d_bblo, nbd * 4)) || (s = alloc(d_bbhi, nbd * 4)) || (s = alloc(d_amin, nbd * 4)) ||
         (s = alloc(d_amax, nbd * 4)) || (s = alloc(d_nin, nb * 4)) || (s = alloc(d_nasg, nb * 4)) ||
-        (s = alloc(d_nexcl, nn * 4)))
+        (s = alloc(d_nexcl, nn * 4)) || (s = alloc(d_far, nb * 8)))
       return s;
     s = kc_tighten(h, &act, &nd, a_bt, wr ? &rf : nullptr, d_bblo.as<float>(), d_bbhi.as<float>(),
                    d_nin.as<uint32_t>(), d_amin.as<float>(), d_amax.as<float>(),
-                   d_nasg.as<uint32_t>(), d_nexcl.as<uint32_t>(), nullptr, st);
+                   d_nasg.as<uint32_t>(), d_nexcl.as<uint32_t>(),
+                   o.use_bt && o.max_refs > 0 ? d_far.as<int64_t>() : nullptr, nullptr, st);
     if (s) return s;
     res->passes++;
     ta.bbl.resize(nbd);
@@ -354,8 +418,44 @@ struct Solver {
     if ((s = down(ta.bbl.data(), d_bblo, nbd * 4)) || (s = down(ta.bbh.data(), d_bbhi, nbd * 4)) ||
         (s = down(ta.amn.data(), d_amin, nbd * 4)) || (s = down(ta.amx.data(), d_amax, nbd * 4)) ||
         (s = down(ta.nin.data(), d_nin, nb * 4)) || (s = down(ta.nasg.data(), d_nasg, nb * 4)) ||
-        (s = down(ta.nex.data(), d_nexcl, nn * 4)) || (s = sync("tighten")))
+        (s = down(ta.nex.data(), d_nexcl, nn * 4)))
       return s;
+    std::vector<int64_t> far(nb, -1);
+    const bool want_far = o.use_bt && o.max_refs > 0;
+    if (want_far && (s = down(far.data(), d_far, nb * 8))) return s;
+    if ((s = sync("tighten"))) return s;
+    if (want_far) {
+      // coordinates and original ids of the new refs, gathered before any
+      // sample reduction moves the active samples
+      std::vector<int64_t> ids;
+      for (size_t b = 0; b < nb; ++b)
+        if (far[b] >= 0) ids.push_back(far[b]);
+      std::vector<float> coords(ids.size() * D);
+      std::vector<int64_t> orig(ids.size());
+      if (!ids.empty()) {
+        if ((s = up(d_ids, ids.data(), ids.size() * 8)) || (s = alloc(d_coords, ids.size() * D * 4)) ||
+            (s = alloc(d_orig, ids.size() * 8)))
+          return s;
+        if ((s = kc_gather(h, &act, d_ids.as<int64_t>(), (int)ids.size(), idx, d_coords.as<float>(),
+                           d_orig.as<int64_t>(), st)))
+          return s;
+        if ((s = down(coords.data(), d_coords, coords.size() * 4)) ||
+            (s = down(orig.data(), d_orig, orig.size() * 8)) || (s = sync("new refs")))
+          return s;
+      }
+      size_t q = 0;
+      for (int i = 0; i < nn; ++i) {
+        Node *m = batch[i];
+        m->new_ref.assign((size_t)K * D, 0.f);
+        m->new_rid.assign(K, -1);
+        for (int k = 0; k < K; ++k)
+          if (far[(size_t)i * K + k] >= 0) {
+            std::memcpy(&m->new_ref[(size_t)k * D], &coords[q * D], D * 4);
+            m->new_rid[k] = orig[q];
+            ++q;
+          }
+      }
+    }
 
     const double sa = o.use_bt ? std::sqrt(a_bt) * (1.0 + 0x1p-50) : INFINITY;
     alive.assign(nn, 1);
@@ -379,10 +479,11 @@ struct Solver {
               amax = ta.amx[q];
               amin = ta.amn[q];
             }
-            if (seeds) {
-              amax = std::max(amax, (double)seed_coords[k * D + a]);
-              amin = std::min(amin, (double)seed_coords[k * D + a]);
-            }
+            if (!m->roff.empty())
+              for (int r = m->roff[k]; r < m->roff[k + 1]; ++r) {
+                amax = std::max(amax, (double)m->ref[(size_t)r * D + a]);
+                amin = std::min(amin, (double)m->ref[(size_t)r * D + a]);
+              }
             if (std::isfinite(amax)) {
               const double v = nextafter(amax - sa, -INFINITY);
               L = std::max(L, kc_round_up_f32(v));
@@ -407,25 +508,29 @@ struct Solver {
   // ---------------------------------------------------- sample reduction --
   kc_status reduce(const std::vector<Node *> &extra) {
     std::vector<const std::vector<float> *> los, his;
+    std::vector<const Node *> ns;
     double beta = INFINITY;
     const double thr = prune_thr();
     for (Node *m : heap)
       if (m->lb < thr) {
         los.push_back(&m->lo);
         his.push_back(&m->hi);
+        ns.push_back(m);
         beta = std::min(beta, m->lb);
       }
     for (Node *m : extra) {
       los.push_back(&m->lo);
       his.push_back(&m->hi);
+      ns.push_back(m);
       beta = std::min(beta, m->lb);
     }
     if (los.empty()) return KC_OK;
     kc_nodes nd;
     kc_refs rf;
-    const bool wr = seeds && o.use_bt;
-    kc_status s = upload_nodes(los, his, &nd, &rf, wr);
+    bool wr = false;
+    kc_status s = upload_nodes(los, his, &nd);
     if (s) return s;
+    if (o.use_bt && (s = upload_refs(ns, &rf, &wr))) return s;
     const int nxt = cur == 0 ? 1 : 0;
     const size_t bytes = (size_t)D * X0->ld * 4;
     if (!xbuf[nxt].ensure(bytes) || !ibuf[nxt].ensure((size_t)X0->ld * 4))
@@ -502,7 +607,9 @@ struct Solver {
     const int q = k * D + a;
     const double mean_l = pc_cnt[0][q] ? pc_sum[0][q] / pc_cnt[0][q] : 0.0;
     const double mean_r = pc_cnt[1][q] ? pc_sum[1][q] / pc_cnt[1][q] : 0.0;
-    int nref = seeds ? K : 0;
+    int nref = 0;
+    if (!m->roff.empty())
+      for (int kk = 0; kk < K; ++kk) nref += m->roff[kk + 1] > m->roff[kk];
     f[0] = (float)(m->depth / 32.0);
     f[1] = (float)(std::log1p((double)heap.size()) / 10.0);
     f[2] = (float)std::min(2.0, m->lb / al);
@@ -626,8 +733,7 @@ struct Solver {
       his.push_back(&chi[c]);
     }
     kc_nodes nd;
-    kc_refs rf;
-    kc_status s = upload_nodes(los, his, &nd, &rf, false);
+    kc_status s = upload_nodes(los, his, &nd);
     if (s) return s;
     const int ne = (int)los.size();
     if ((s = alloc(d_lbsafe, ne * 8)) || (s = alloc(d_cand, (size_t)ne * K * 8))) return s;
@@ -778,6 +884,7 @@ struct Solver {
           c->side = side;
           c->nsplit = m->nsplit;
           if (c->nsplit[k * D + a] < 255) c->nsplit[k * D + a]++;
+          inherit_refs(m, c);
           c->id = next_id++;
           if (symmetry && !apply_symmetry(c->lo, c->hi)) {
             delete c;  // empty box: no solution
@@ -818,8 +925,7 @@ struct Solver {
       his[i] = &ev[i]->hi;
     }
     kc_nodes nd;
-    kc_refs rf;
-    kc_status s = upload_nodes(los, his, &nd, &rf, false);
+    kc_status s = upload_nodes(los, his, &nd);
     if (s) return s;
     if ((s = alloc(d_lbraw, ne * 4)) || (s = alloc(d_lbsafe, ne * 8)) || (s = alloc(d_argmax, ne * 8)) ||
         (s = alloc(d_cand, (size_t)ne * K * 8)))

@@ -35,15 +35,30 @@ struct TightenArgs {
   int64_t span;
   uint32_t *bb_lo, *bb_hi, *asg_min, *asg_max;  // order-preserving encodings
   uint32_t *n_in, *n_asg, *n_excl;
+  uint64_t *asg_far;  // per box: max key (dist to midpoint, ~index); may be null
   int8_t *labels;
 };
 
-template <int D, int KC>
+__device__ __forceinline__ float sqdist(const float *xv, const float *r, int dd, int DM) {
+  float acc = 0.f;
+  for (int a = 0; a < DM; ++a) {
+    if (a < dd) {
+      const float t = xv[a] - r[a];
+      acc = (a == 0) ? t * t : __builtin_fmaf(t, t, acc);
+    }
+  }
+  return acc;
+}
+
+// S samples per lane per tile (16-byte loads when S = 4), KC boxes per chunk
+// with their aggregates in registers. With all boxes of the node in one chunk
+// the box distances of the center-based test also give the inside flags.
+template <int D, int KC, int S>
 __global__ __launch_bounds__(WG) void k_tighten(TightenArgs A) {
   constexpr int DM = D ? D : 16;
   const int dd = D ? D : A.d;
   extern __shared__ float sm[];  // boxes [k_max][2*DM] then refs [*][DM]
-  __shared__ int s_b0, s_cnt, s_allref, s_r0, s_rtot;
+  __shared__ int s_b0, s_cnt, s_allref;
   __shared__ int s_rbeg[64], s_rcnt[64];
 
   const int tid = threadIdx.x, lane = tid & 63;
@@ -59,24 +74,19 @@ __global__ __launch_bounds__(WG) void k_tighten(TightenArgs A) {
     s_b0 = b0;
     s_cnt = cnt;
     int all = cnt > 0 && A.ref_off != nullptr;
-    int r0 = 0, tot = 0;
-    if (A.ref_off) r0 = kcd::clampi(A.ref_off[b0], 0, A.n_refs);
+    int tot = 0;
     for (int k = 0; k < cnt; ++k) {
-      int rb = 0, rc = 0;
+      int rc = 0;
       if (A.ref_off) {
-        rb = kcd::clampi(A.ref_off[b0 + k], 0, A.n_refs);
+        const int rb = kcd::clampi(A.ref_off[b0 + k], 0, A.n_refs);
         const int re = kcd::clampi(A.ref_off[b0 + k + 1], rb, A.n_refs);
         rc = min(re - rb, A.max_refs);
       }
       s_rbeg[k] = tot;  // position in the LDS copy
       s_rcnt[k] = rc;
-      s_rcnt[k] = rc;
       tot += rc;
       if (rc == 0) all = 0;
-      (void)rb;
     }
-    s_r0 = r0;
-    s_rtot = tot;
     s_allref = all;
   }
   __syncthreads();
@@ -106,12 +116,15 @@ __global__ __launch_bounds__(WG) void k_tighten(TightenArgs A) {
   __syncthreads();
 
   const int c0 = chunk * A.kc;
+  const bool single = A.n_chunks == 1;
   float bmin[KC][DM], bmax[KC][DM], amin[KC][DM], amax[KC][DM];
   uint32_t nin[KC], nasg[KC];
+  uint64_t far[KC];
 #pragma unroll
   for (int kk = 0; kk < KC; ++kk) {
     nin[kk] = 0;
     nasg[kk] = 0;
+    far[kk] = 0;
 #pragma unroll
     for (int a = 0; a < DM; ++a) {
       bmin[kk][a] = INFINITY;
@@ -126,98 +139,142 @@ __global__ __launch_bounds__(WG) void k_tighten(TightenArgs A) {
 
   const int64_t s_lo = (int64_t)split * A.span;
   const int64_t s_hi = min(A.n, s_lo + A.span);
-  for (int64_t s = s_lo + tid; s < s_hi; s += WG) {
-    float xv[DM];
+  for (int64_t base = s_lo + (int64_t)tid * S; base < s_hi; base += (int64_t)WG * S) {
+    float xs[S][DM];
+    const bool full = base + S <= s_hi;
 #pragma unroll
-    for (int a = 0; a < DM; ++a) xv[a] = a < dd ? A.x[(int64_t)a * A.ld + s] : 0.f;
-
-    // Center-based assignment (Lemma 1).
-    int n_out = 0, keep = -1;
-    for (int k = 0; k < cnt; ++k) {
-      float acc = 0.f;
+    for (int a = 0; a < DM; ++a) {
+      if (a < dd) {
+        const float *p = A.x + (int64_t)a * A.ld + base;
+        if (full && S == 4) {
+          const float4 v = *reinterpret_cast<const float4 *>(p);
+          xs[0][a] = v.x;
+          xs[1 % S][a] = v.y;
+          xs[2 % S][a] = v.z;
+          xs[3 % S][a] = v.w;
+        } else if (full && S == 2) {
+          const float2 v = *reinterpret_cast<const float2 *>(p);
+          xs[0][a] = v.x;
+          xs[1 % S][a] = v.y;
+        } else {
 #pragma unroll
-      for (int a = 0; a < DM; ++a) {
-        if (a < dd) {
-          const float c = kcd::med3(bx[k * 2 * DM + 2 * a], xv[a], bx[k * 2 * DM + 2 * a + 1]);
-          const float t = xv[a] - c;
-          acc = (a == 0) ? t * t : __builtin_fmaf(t, t, acc);
+          for (int i = 0; i < S; ++i) xs[i][a] = (base + i < s_hi) ? p[i] : 0.f;
         }
+      } else {
+#pragma unroll
+        for (int i = 0; i < S; ++i) xs[i][a] = 0.f;
       }
-      if (acc > A.t_center)
-        ++n_out;
-      else
-        keep = k;
     }
-    int label = -1;
-    if (n_out == cnt)
-      label = -2;
-    else if (n_out == cnt - 1)
-      label = keep;
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+      if (base + i >= s_hi) break;
+      const float *xv = xs[i];
+      const uint32_t sid = (uint32_t)(base + i);
 
-    // Sample-based assignment (Lemma 2), only for unassigned samples.
-    if (label == -1 && allref) {
-      int n_far = 0, rest_k = -1;
-      for (int k = 0; k < cnt; ++k) {
-        bool far = false;
-        for (int r = 0; r < s_rcnt[k]; ++r) {
-          const float *rr = rf + (s_rbeg[k] + r) * DM;
+      // Center-based assignment (Lemma 1); in the single-chunk case the same
+      // pass records which boxes hold the sample.
+      int n_out = 0, keep = -1;
+      uint32_t inmask = 0;
+      if (single) {
+#pragma unroll
+        for (int k = 0; k < KC; ++k) {
+          if (k < cnt) {
+            float acc = 0.f;
+            bool in = true;
+#pragma unroll
+            for (int a = 0; a < DM; ++a) {
+              if (a < dd) {
+                const float c = kcd::med3(bx[k * 2 * DM + 2 * a], xv[a], bx[k * 2 * DM + 2 * a + 1]);
+                in = in && (c == xv[a]);
+                const float t = xv[a] - c;
+                acc = (a == 0) ? t * t : __builtin_fmaf(t, t, acc);
+              }
+            }
+            if (acc > A.t_center)
+              ++n_out;
+            else
+              keep = k;
+            inmask |= (uint32_t)in << k;
+          }
+        }
+      } else {
+        for (int k = 0; k < cnt; ++k) {
           float acc = 0.f;
 #pragma unroll
           for (int a = 0; a < DM; ++a) {
             if (a < dd) {
-              const float t = xv[a] - rr[a];
+              const float c = kcd::med3(bx[k * 2 * DM + 2 * a], xv[a], bx[k * 2 * DM + 2 * a + 1]);
+              const float t = xv[a] - c;
               acc = (a == 0) ? t * t : __builtin_fmaf(t, t, acc);
             }
           }
-          far = far || (acc > A.t_sample);
+          if (acc > A.t_center)
+            ++n_out;
+          else
+            keep = k;
         }
-        if (far)
-          ++n_far;
-        else
-          rest_k = k;
+#pragma unroll
+        for (int kk = 0; kk < KC; ++kk) {
+          const int k = c0 + kk;
+          if (k < cnt) {
+            bool in = true;
+#pragma unroll
+            for (int a = 0; a < DM; ++a)
+              if (a < dd) in = in && (bx[k * 2 * DM + 2 * a] <= xv[a]) && (xv[a] <= bx[k * 2 * DM + 2 * a + 1]);
+            inmask |= (uint32_t)in << kk;
+          }
+        }
       }
-      if (n_far == cnt - 1) label = rest_k;
-    }
-    if (write_labels) A.labels[s] = (int8_t)label;
-    nex += (label == -2);
+      int label = -1;
+      if (n_out == cnt)
+        label = -2;
+      else if (n_out == cnt - 1)
+        label = keep;
+
+      // Sample-based assignment (Lemma 2), only for unassigned samples.
+      if (label == -1 && allref) {
+        int n_farc = 0, rest_k = -1;
+        for (int k = 0; k < cnt; ++k) {
+          bool fr = false;
+          for (int r = 0; r < s_rcnt[k]; ++r) fr = fr || (sqdist(xv, rf + (s_rbeg[k] + r) * DM, dd, DM) > A.t_sample);
+          if (fr)
+            ++n_farc;
+          else
+            rest_k = k;
+        }
+        if (n_farc == cnt - 1) label = rest_k;
+      }
+      if (write_labels) A.labels[sid] = (int8_t)label;
+      nex += (label == -2);
 
 #pragma unroll
-    for (int kk = 0; kk < KC; ++kk) {
-      const int k = c0 + kk;
-      if (k < cnt) {
-        if (label == k) {
-          ++nasg[kk];
-#pragma unroll
-          for (int a = 0; a < DM; ++a) {
-            amin[kk][a] = fminf(amin[kk][a], xv[a]);
-            amax[kk][a] = fmaxf(amax[kk][a], xv[a]);
-          }
-        }
-        // S_+^k: inside box k and within the ball of every ref of box k.
-        bool in = true;
-#pragma unroll
-        for (int a = 0; a < DM; ++a)
-          if (a < dd) in = in && (bx[k * 2 * DM + 2 * a] <= xv[a]) && (xv[a] <= bx[k * 2 * DM + 2 * a + 1]);
-        if (in) {
-          for (int r = 0; r < s_rcnt[k]; ++r) {
-            const float *rr = rf + (s_rbeg[k] + r) * DM;
-            float acc = 0.f;
+      for (int kk = 0; kk < KC; ++kk) {
+        const int k = c0 + kk;
+        if (k < cnt) {
+          if (label == k) {
+            ++nasg[kk];
+            float dm = 0.f;
 #pragma unroll
             for (int a = 0; a < DM; ++a) {
-              if (a < dd) {
-                const float t = xv[a] - rr[a];
-                acc = (a == 0) ? t * t : __builtin_fmaf(t, t, acc);
-              }
+              amin[kk][a] = fminf(amin[kk][a], xv[a]);
+              amax[kk][a] = fmaxf(amax[kk][a], xv[a]);
+              const float w = xv[a] - 0.5f * (bx[k * 2 * DM + 2 * a] + bx[k * 2 * DM + 2 * a + 1]);
+              dm = (a == 0) ? w * w : __builtin_fmaf(w, w, dm);
             }
-            in = in && (acc <= A.t_ball);
+            const uint64_t key = kcd::key_max(dm, sid);
+            far[kk] = key > far[kk] ? key : far[kk];
           }
-        }
-        if (in) {
-          ++nin[kk];
+          // S_+^k: inside box k and within the ball of every ref of box k.
+          bool in = (inmask >> (single ? k : kk)) & 1u;
+          if (in)
+            for (int r = 0; r < s_rcnt[k]; ++r) in = in && (sqdist(xv, rf + (s_rbeg[k] + r) * DM, dd, DM) <= A.t_ball);
+          if (in) {
+            ++nin[kk];
 #pragma unroll
-          for (int a = 0; a < DM; ++a) {
-            bmin[kk][a] = fminf(bmin[kk][a], xv[a]);
-            bmax[kk][a] = fmaxf(bmax[kk][a], xv[a]);
+            for (int a = 0; a < DM; ++a) {
+              bmin[kk][a] = fminf(bmin[kk][a], xv[a]);
+              bmax[kk][a] = fmaxf(bmax[kk][a], xv[a]);
+            }
           }
         }
       }
@@ -230,10 +287,12 @@ __global__ __launch_bounds__(WG) void k_tighten(TightenArgs A) {
     const int k = c0 + kk;
     const uint32_t ci = kcd::wave_sum_u32(nin[kk]);
     const uint32_t ca = kcd::wave_sum_u32(nasg[kk]);
+    const uint64_t fk = kcd::wave_max_u64(far[kk]);
     if (k < cnt) {
       const int64_t b = s_b0 + k;
       if (lane == 0 && ci) atomicAdd(&A.n_in[b], ci);
       if (lane == 0 && ca) atomicAdd(&A.n_asg[b], ca);
+      if (lane == 0 && ca && A.asg_far) atomicMax((unsigned long long *)&A.asg_far[b], (unsigned long long)fk);
     }
 #pragma unroll
     for (int a = 0; a < DM; ++a) {
@@ -261,7 +320,7 @@ __global__ __launch_bounds__(WG) void k_tighten(TightenArgs A) {
 }
 
 __global__ void k_tighten_init(uint32_t *bb_lo, uint32_t *bb_hi, uint32_t *amn, uint32_t *amx,
-                               uint32_t *n_in, uint32_t *n_asg, int64_t nbd, int nb,
+                               uint32_t *n_in, uint32_t *n_asg, uint64_t *far, int64_t nbd, int nb,
                                uint32_t *n_excl, int nn) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < nbd) {
@@ -273,11 +332,13 @@ __global__ void k_tighten_init(uint32_t *bb_lo, uint32_t *bb_hi, uint32_t *amn, 
   if (i < nb) {
     n_in[i] = 0;
     n_asg[i] = 0;
+    if (far) far[i] = 0;
   }
   if (i < nn) n_excl[i] = 0;
 }
 
-__global__ void k_tighten_decode(uint32_t *a, uint32_t *b, uint32_t *c, uint32_t *e, int64_t nbd) {
+__global__ void k_tighten_decode(uint32_t *a, uint32_t *b, uint32_t *c, uint32_t *e, int64_t nbd,
+                                 uint64_t *far, int nb) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < nbd) {
     a[i] = __float_as_uint(kcd::fdec(a[i]));
@@ -285,22 +346,45 @@ __global__ void k_tighten_decode(uint32_t *a, uint32_t *b, uint32_t *c, uint32_t
     c[i] = __float_as_uint(kcd::fdec(c[i]));
     e[i] = __float_as_uint(kcd::fdec(e[i]));
   }
+  if (far && i < nb) {
+    const uint64_t k = far[i];
+    reinterpret_cast<int64_t *>(far)[i] = k ? (int64_t)(~(uint32_t)(k & 0xffffffffu)) : -1;
+  }
 }
 
-#define KCT_CASE(DV, KCV)                                                 \
-  if (d == DV && kc == KCV) {                                             \
-    k_tighten<(DV <= 8 ? DV : 0), KCV><<<grid, WG, lds, st>>>(A);         \
-    return KC_OK;                                                         \
+// samples per lane: 16-byte loads for up to 4 attributes, 8-byte beyond
+#define KCT_S(DV) ((DV) > 0 && (DV) <= 4 ? 4 : 2)
+#define KCT_CASE(DV, KCV)                                                      \
+  if (d == DV && kc == KCV) {                                                  \
+    k_tighten<DV, KCV, KCT_S(DV)><<<grid, WG, lds, st>>>(A);                   \
+    return KC_OK;                                                              \
   }
-#define KCT_D(DV) KCT_CASE(DV, 1) KCT_CASE(DV, 2) KCT_CASE(DV, 4) KCT_CASE(DV, 8)
+#define KCT_D(DV) \
+  KCT_CASE(DV, 1) KCT_CASE(DV, 2) KCT_CASE(DV, 3) KCT_CASE(DV, 4) KCT_CASE(DV, 5) KCT_CASE(DV, 6) KCT_CASE(DV, 8)
+
+static const int kKC[] = {1, 2, 3, 4, 5, 6, 8};
 
 static kc_status launch(int d, int kc, const TightenArgs &A, int grid, size_t lds, hipStream_t st) {
   KCT_D(1) KCT_D(2) KCT_D(3) KCT_D(4) KCT_D(5) KCT_D(6) KCT_D(7) KCT_D(8)
   if (d > 8) {
-    if (kc == 1) { k_tighten<0, 1><<<grid, WG, lds, st>>>(A); return KC_OK; }
-    if (kc == 2) { k_tighten<0, 2><<<grid, WG, lds, st>>>(A); return KC_OK; }
+    if (kc == 1) { k_tighten<0, 1, 2><<<grid, WG, lds, st>>>(A); return KC_OK; }
+    if (kc == 2) { k_tighten<0, 2, 2><<<grid, WG, lds, st>>>(A); return KC_OK; }
   }
   return KC_EUNSUPPORTED;
+}
+
+// Boxes per chunk: all boxes of a node when their aggregates fit in about 160
+// registers, else the largest compiled chunk that does.
+static int choose_kc(int d, int k_max) {
+  const int DM = d <= 8 ? d : 16;
+  const int cap = d > 8 ? 2 : 8;
+  int best = 1;
+  for (int c : kKC) {
+    if (c > cap || c * (4 * DM + 4) > 160) break;
+    best = c;
+    if (c >= k_max) break;
+  }
+  return best;
 }
 
 }  // namespace kct
@@ -310,7 +394,7 @@ using namespace kct;
 extern "C" kc_status kc_tighten(kc_handle *h, const kc_points *pts, const kc_nodes *nodes,
                                 double alpha, const kc_refs *refs, float *bb_lo, float *bb_hi,
                                 uint32_t *n_in, float *asg_min, float *asg_max, uint32_t *n_asg,
-                                uint32_t *n_excl, int8_t *labels, void *stream) {
+                                uint32_t *n_excl, int64_t *asg_far, int8_t *labels, void *stream) {
   if (!h) return KC_EINVAL;
   kc_status s = kc_validate_points(h, pts);
   if (s != KC_OK) return s;
@@ -324,20 +408,17 @@ extern "C" kc_status kc_tighten(kc_handle *h, const kc_points *pts, const kc_nod
   KC_RETURN_IF(std::isnan(alpha) || alpha < 0, h, KC_EINVAL, "alpha must be >= 0");
   hipStream_t st = (hipStream_t)stream;
   const int d = pts->d, DM = d <= 8 ? d : 16;
-  // boxes per chunk: as many as fit in about 112 registers of aggregates
-  int kc = 8;
-  while (kc > 1 && kc * (4 * DM + 2) > 112) kc /= 2;
-  if (d > 8 && kc > 2) kc = 2;
-  while (kc > 1 && kc / 2 >= nodes->k_max) kc /= 2;
+  const int kc = choose_kc(d, nodes->k_max);
   const int n_chunks = (nodes->k_max + kc - 1) / kc;
   const int max_refs = refs ? refs->max_per_box : 0;
   const size_t lds = ((size_t)nodes->k_max * 2 * DM + (size_t)nodes->k_max * max_refs * DM) * 4;
   KC_RETURN_IF(lds > h->lds_per_block, h, KC_EUNSUPPORTED, "boxes and refs of a node exceed LDS");
+  const int S = (d <= 4) ? 4 : 2;
   const int64_t units = (int64_t)nodes->n_nodes * n_chunks;
   const int64_t target = (int64_t)h->n_cu * 8;
   int64_t splits = (target + units - 1) / units;
   int64_t span = (pts->n + splits - 1) / splits;
-  span = (span + WG - 1) / WG * WG;
+  span = (span + WG * S - 1) / (WG * S) * (WG * S);
   splits = (pts->n + span - 1) / span;
   const int64_t grid = splits * units;
   KC_RETURN_IF(grid > 0x7fffffff, h, KC_EUNSUPPORTED, "grid too large");
@@ -348,7 +429,7 @@ extern "C" kc_status kc_tighten(kc_handle *h, const kc_points *pts, const kc_nod
   if (nmax > 0)
     k_tighten_init<<<(nmax + 255) / 256, 256, 0, st>>>(
         (uint32_t *)bb_lo, (uint32_t *)bb_hi, (uint32_t *)asg_min, (uint32_t *)asg_max, n_in,
-        n_asg, nbd, nodes->n_boxes, n_excl, nodes->n_nodes);
+        n_asg, (uint64_t *)asg_far, nbd, nodes->n_boxes, n_excl, nodes->n_nodes);
   s = kc_check_launch(h, "k_tighten_init");
   if (s != KC_OK) return s;
 
@@ -380,14 +461,15 @@ extern "C" kc_status kc_tighten(kc_handle *h, const kc_points *pts, const kc_nod
   A.n_in = n_in;
   A.n_asg = n_asg;
   A.n_excl = n_excl;
+  A.asg_far = (uint64_t *)asg_far;
   A.labels = labels;
   s = launch(d, kc, A, (int)grid, lds, st);
   KC_RETURN_IF(s != KC_OK, h, s, "no tighten variant for d=%d kc=%d", d, kc);
   s = kc_check_launch(h, "k_tighten");
   if (s != KC_OK) return s;
-  if (nbd > 0)
-    k_tighten_decode<<<(nbd + 255) / 256, 256, 0, st>>>((uint32_t *)bb_lo, (uint32_t *)bb_hi,
-                                                        (uint32_t *)asg_min,
-                                                        (uint32_t *)asg_max, nbd);
+  if (nmax > 0)
+    k_tighten_decode<<<(nmax + 255) / 256, 256, 0, st>>>((uint32_t *)bb_lo, (uint32_t *)bb_hi,
+                                                         (uint32_t *)asg_min, (uint32_t *)asg_max,
+                                                         nbd, (uint64_t *)asg_far, nodes->n_boxes);
   return kc_check_launch(h, "k_tighten_decode");
 }

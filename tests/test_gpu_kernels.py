@@ -217,6 +217,19 @@ def test_tighten_parity(kc, seed, n, d, k, nn, with_refs):
         assert np.array_equal(res["n_asg"][sl], o["n_asg"])
         for key in ("bb_lo", "bb_hi", "asg_min", "asg_max"):
             assert np.array_equal(res[key][sl].astype(np.float64), o[key]), key
+        # farthest assigned sample from each box midpoint (float32 midpoint on
+        # the device): an assigned sample of that box at the oracle's distance
+        # up to rounding
+        lab = o["labels"]
+        for j in range(k):
+            fo, fg = o["asg_far"][j], res["asg_far"][off[m] + j]
+            if fo < 0:
+                assert fg == -1
+                continue
+            assert lab[fg] == j
+            mid = 0.5 * (lo[off[m] + j].astype(np.float64) + hi[off[m] + j])
+            dist = lambda s_: ((X64[s_] - mid) ** 2).sum()
+            assert dist(fg) >= dist(fo) * (1 - 4 * g) - 1e-6 * (1 + np.abs(mid).max())
     assert unstable_nodes <= max(1, nn // 3)
 
 

@@ -85,7 +85,8 @@ def test_solve_one_dimensional(kc):
 
 
 @pytest.mark.parametrize("opts", [dict(use_bt=False, i_sr=0), dict(i_sr=0), dict(use_seeds=False),
-                                  dict(batch=1), dict(batch=256, i_sr=1)])
+                                  dict(batch=1), dict(batch=256, i_sr=1), dict(max_refs=0),
+                                  dict(max_refs=1)])
 def test_solve_variants_agree(kc, opts):
     X = datagen.small_mixture(2)
     X64 = X.astype(np.float64)
@@ -94,6 +95,18 @@ def test_solve_variants_agree(kc, opts):
     kw.update(opts)
     r = kc.solve(kc.to_device_soa(X), len(X), 3, **kw)
     _check(X64, r, opt)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_solve_medium_instances(kc, seed):
+    """20,000 samples, K = 3: instances the reference policy closes in a few
+    hundred nodes."""
+    X = datagen.gaussian_mixture(20000, 2, 3, 0.05, seed)
+    X64 = X.astype(np.float64)
+    ro = oracle.solve(X64, 3)
+    r = kc.solve(kc.to_device_soa(X), len(X), 3, batch=32, i_sr=2)
+    assert r["status"] == 0
+    _check(X64, r, ro["obj"])
 
 
 def test_solve_node_limit_keeps_valid_bounds(kc):

@@ -172,9 +172,9 @@ def test_solve_vs_brute_force_slice(orc, seed):
     X = datagen.small_mixture(seed).astype(np.float64)[:30]
     for k in (2, 3, 4):
         best, _ = orc.brute_force(X, k)
-        for use_bt in (True, False):
-            r = orc.solve(X, k, use_bt=use_bt, i_sr=3)
-            assert r["obj"] == best, (k, use_bt)
+        for use_bt, mr in ((True, 50), (True, 0), (False, 50)):
+            r = orc.solve(X, k, use_bt=use_bt, i_sr=3, max_refs=mr)
+            assert r["obj"] == best, (k, use_bt, mr)
             assert r["lb"] == best
 
 
@@ -309,6 +309,9 @@ def test_tightening_aggregates_by_hand(orc):
     assert agg["asg_min"][:, 0].tolist() == [0.0, 0.875] and agg["asg_max"][:, 0].tolist() == [0.5, 1.0]
     assert agg["n_in"].tolist() == [2, 2]
     assert agg["bb_lo"][:, 0].tolist() == [0.0, 0.875] and agg["bb_hi"][:, 0].tolist() == [0.25, 1.0]
+    # farthest assigned from the midpoints .125 and .9375: x = .5 (index 2);
+    # .875 and 1.0 tie at .0625 -> the lower index 3
+    assert agg["asg_far"].tolist() == [2, 3]
     inf, lo2, hi2 = orc.tightened_box(lo, hi, alpha, agg)
     # box0: bbox [0, .25] cap [.5 - .25, 0 + .25] = [.25, .25]; box1 unchanged
     assert not inf
