@@ -144,10 +144,28 @@ std::vector<kc_tile> kc_bound_variants(int d, bool with_cand, int k_max) {
   return v;
 }
 
+static bool cand_compiled(int S, int NG, int KC) {
+#define KCB_T4(SV, NGV, KCV) \
+  if (S == SV && NG == NGV && KC == KCV) return true;
+  KCB_CAND_VARIANTS(KCB_T4)
+#undef KCB_T4
+  return false;
+}
+
+// Candidate variants keep NG x KC running minima per lane; the default holds
+// 32 of them (NG = 32 / KC nodes per workgroup, fewer for small batches).
+static kc_tile cand_default(int n_nodes, int k_max) {
+  const int kc = cand_kc(k_max);
+  int ng = kc >= 64 ? 1 : 32 / kc;
+  while (ng > 1 && ng / 2 >= n_nodes) ng /= 2;
+  while (ng > 1 && !cand_compiled(kc >= 16 ? 1 : 2, ng, kc)) ng /= 2;
+  return {kc >= 16 ? 1 : 2, ng, 8};
+}
+
 kc_tile kc_default_tile(kc_handle *h, int d, bool with_cand, int n_nodes, int k_max, int64_t n) {
   (void)h;
   (void)n;
-  if (with_cand) return {k_max <= 8 ? 2 : 1, 1, 8};
+  if (with_cand) return cand_default(n_nodes, k_max);
   if (n_nodes == 1) return {d <= 4 ? 8 : 4, 1, 8};
   if (n_nodes <= 3) return {4, 2, 8};
   if (n_nodes <= 7) return {4, 4, 8};
@@ -163,11 +181,7 @@ kc_status kc_launch_bound(kc_handle *h, const kc_points *p, int mode, int n_node
   kc_tile t = t0;
   const int DM = dmax_of(p->d);
   const int KC = with_cand ? cand_kc(k_max) : 0;
-  if (with_cand) {
-    // candidate variants exist for NG = 1 only
-    t.NG = 1;
-    if (KC >= 16) t.S = 1;
-  }
+  if (with_cand && !cand_compiled(t.S, t.NG, KC)) t = cand_default(n_nodes, k_max);
   if (point) {
     if (!((t.S == 4 && t.NG == 1) || (t.S == 2 && t.NG == 4) || (t.S == 2 && t.NG == 8)))
       t = n_nodes <= 2 ? kc_tile{4, 1, t.bpc} : kc_tile{2, 4, t.bpc};

@@ -175,32 +175,48 @@ __global__ __launch_bounds__(WG) void k_bound(BoundArgs A) {
 #pragma unroll
         for (int k = 0; k < KC; ++k) {
           if (k < cnt) {
-            float l[DM], h[DM], mid[DM];
+            float l[DM], h[DM];
 #pragma unroll
             for (int a = 0; a < DM; ++a) {
               l[a] = bx[k * 2 * DM + 2 * a];
               h[a] = bx[k * 2 * DM + 2 * a + 1];
-              mid[a] = 0.5f * (l[a] + h[a]);
             }
+            bool in[S];
 #pragma unroll
             for (int i = 0; i < S; ++i) {
-              float acc = 0.0f, dm = 0.0f;
-              bool in = base + i < s_hi;
+              float acc = 0.0f;
+              in[i] = base + i < s_hi;
 #pragma unroll
               for (int a = 0; a < DM; ++a) {
                 if (a < dd) {
                   const float c = kcd::med3(l[a], xv[a][i], h[a]);
-                  in = in && (c == xv[a][i]);
+                  in[i] = in[i] && (c == xv[a][i]);
                   const float t = xv[a][i] - c;
                   acc = (a == 0) ? t * t : __builtin_fmaf(t, t, acc);
-                  const float w = xv[a][i] - mid[a];
-                  dm = (a == 0) ? w * w : __builtin_fmaf(w, w, dm);
                 }
               }
               best[i] = fminf(best[i], acc);
-              if (in && dm < cmin[jn][k]) {
-                cmin[jn][k] = dm;
-                cidx[jn][k] = (uint32_t)(base + i);
+            }
+            // distance to the midpoint only when some lane holds a sample
+            // inside the box (a wavefront-uniform branch)
+            bool any = false;
+#pragma unroll
+            for (int i = 0; i < S; ++i) any = any || in[i];
+            if (__ballot(any)) {
+#pragma unroll
+              for (int i = 0; i < S; ++i) {
+                float dm = 0.0f;
+#pragma unroll
+                for (int a = 0; a < DM; ++a) {
+                  if (a < dd) {
+                    const float w = xv[a][i] - 0.5f * (l[a] + h[a]);
+                    dm = (a == 0) ? w * w : __builtin_fmaf(w, w, dm);
+                  }
+                }
+                if (in[i] && dm < cmin[jn][k]) {
+                  cmin[jn][k] = dm;
+                  cidx[jn][k] = (uint32_t)(base + i);
+                }
               }
             }
           }
@@ -338,7 +354,8 @@ kc_status launch_variant(int D, int S, int NG, int KC, bool point, const BoundAr
 // (S, NG, KC) for the lower bound with candidates (KC >= boxes per node).
 #define KCB_LB_VARIANTS(X) X(8, 1) X(4, 1) X(2, 1) X(4, 2) X(4, 4) X(2, 4) X(4, 8) X(2, 8) X(2, 16) X(1, 16)
 #define KCB_PT_VARIANTS(X) X(4, 1) X(2, 4) X(2, 8)
-#define KCB_CAND_VARIANTS(X) X(2, 1, 4) X(2, 1, 8) X(1, 1, 16) X(1, 1, 64)
+#define KCB_CAND_VARIANTS(X) \
+  X(2, 8, 4) X(2, 4, 4) X(2, 1, 4) X(2, 4, 8) X(2, 2, 8) X(2, 1, 8) X(1, 2, 16) X(1, 1, 16) X(1, 1, 64)
 
 #define KCB_LB_CASE(SV, NGV) \
   if (S == SV && NG == NGV) { k_bound<DV_, SV, NGV, 0, false><<<g, b, lds, st>>>(A); return KC_OK; }
