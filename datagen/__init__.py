@@ -169,8 +169,7 @@ def learned_instance(seed: int, n: int, d: int = 5, k: int | None = None):
     K ~ U{4..8} drawn from the seed unless given. Returns ``(x, K)``.
     """
     if k is None:
-        rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 0x4B])))
-        k = int(rng.integers(4, 9))
+        k = learned_instance_k(seed)
     return gaussian_mixture(n, d, k, 0.1, seed), k
 
 
@@ -240,3 +239,17 @@ def uniform_points_device(n: int, d: int, seed: int, device="cuda", ld: int | No
         m = min(step, n - a0)
         x[:, a0:a0 + m] = torch.rand((d, m), generator=g, device=device, dtype=torch.float64).to(torch.float32)
     return x
+
+
+def learned_instance_k(seed: int) -> int:
+    """K ~ U{4..8} of the learned-branching instance with this seed."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 0x4B])))
+    return int(rng.integers(4, 9))
+
+
+def learned_instance_device(seed: int, n: int, d: int = 5, k: int | None = None, device="cuda"):
+    """Device-side learned-branching instance (see ``learned_instance``):
+    returns ``(x [d, ld] float32 tensor, K)``."""
+    if k is None:
+        k = learned_instance_k(seed)
+    return gaussian_mixture_device(n, d, k, 0.1, seed, device=device), k

@@ -11,6 +11,12 @@
 // original samples. Nodes are pruned when their rigorous lower bound reaches
 // the incumbent, and every node that leaves the tree records the bound it
 // leaves behind, so the final lower bound is rigorous too.
+//
+// Host <-> device traffic per phase is one packed upload and one packed
+// download through a pinned staging arena; the coordinates of candidates and
+// new refs are gathered on the device, so a pass synchronises twice (after
+// the tightening phase and after the bounding phase), plus once for a
+// certificate or a sample reduction.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -30,6 +36,55 @@ namespace {
 
 constexpr int NFEAT = 32;
 
+// Pinned host buffer with a device mirror, bump-allocated per phase: offsets
+// are taken first, then reserve() sizes both sides, then the host side is
+// filled and moved with one copy.
+struct Arena {
+  char *h = nullptr, *d = nullptr;
+  size_t cap = 0, used = 0;
+  ~Arena() {
+    if (h) (void)hipHostFree(h);
+    if (d) (void)hipFree(d);
+  }
+  void reset() { used = 0; }
+  size_t take(size_t bytes) {
+    const size_t o = (used + 255) & ~(size_t)255;
+    used = o + bytes;
+    return o;
+  }
+  bool reserve() {
+    if (used <= cap) return true;
+    if (h || d) {
+      (void)hipDeviceSynchronize();  // earlier work may still use the old buffers
+      if (h) (void)hipHostFree(h);
+      if (d) (void)hipFree(d);
+      h = d = nullptr;
+      cap = 0;
+    }
+    const size_t nb = used + used / 2 + 4096;
+    if (hipHostMalloc((void **)&h, nb, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      h = nullptr;
+      return false;
+    }
+    if (hipMalloc((void **)&d, nb) != hipSuccess) {
+      (void)hipGetLastError();
+      d = nullptr;
+      return false;
+    }
+    cap = nb;
+    return true;
+  }
+  template <class T>
+  T *hp(size_t o) const {
+    return (T *)(h + o);
+  }
+  template <class T>
+  T *dp(size_t o) const {
+    return (T *)(d + o);
+  }
+};
+
 struct DevBuf {
   void *p = nullptr;
   size_t cap = 0;
@@ -44,7 +99,7 @@ struct DevBuf {
       p = nullptr;
       cap = 0;
     }
-    const size_t nb = bytes + bytes / 2 + 256;
+    const size_t nb = bytes + 256;
     if (hipMalloc(&p, nb) != hipSuccess) {
       (void)hipGetLastError();
       p = nullptr;
@@ -122,7 +177,6 @@ struct Solver {
   // root data
   std::vector<float> root_lo, root_hi;
   bool seeds = false, symmetry = false;
-  std::vector<float> seed_coords;  // K*D
 
   std::vector<Node *> heap;
   int64_t next_id = 0, n_branched = 0;
@@ -132,13 +186,11 @@ struct Solver {
   std::vector<double> pc_sum[2];
   std::vector<int> pc_cnt[2];
 
-  // device buffers
-  DevBuf d_off, d_lo, d_hi, d_roff, d_ref;
-  DevBuf d_bblo, d_bbhi, d_nin, d_amin, d_amax, d_nasg, d_nexcl;
-  DevBuf d_lbraw, d_lbsafe, d_argmax, d_cand, d_ids, d_coords, d_orig, d_obj, d_oam;
-  DevBuf d_feat, d_score, d_far;
-
+  Arena in, out;
   double t0 = 0;
+  // wall time per phase (reported with verbose)
+  double t_tighten = 0, t_reduce = 0, t_branch = 0, t_bound = 0;
+  int64_t sr_interval = 0, sr_runs = 0;
 
   Solver(kc_handle *h_, const kc_points *x, const kc_opts *op, kc_result *r)
       : h(h_), X0(x), o(*op), res(r), K(op->k), D(x->d) {
@@ -154,20 +206,19 @@ struct Solver {
     if (e != hipSuccess) return kc_fail(h, KC_EDEVICE, "%s: %s", what, hipGetErrorString(e));
     return KC_OK;
   }
-  kc_status up(DevBuf &b, const void *src, size_t bytes) {
-    if (!b.ensure(bytes)) return kc_fail(h, KC_ENOMEM, "driver buffer of %zu bytes", bytes);
-    if (bytes && hipMemcpyAsync(b.p, src, bytes, hipMemcpyHostToDevice, st) != hipSuccess)
+  kc_status reserve() {
+    if (!in.reserve() || !out.reserve()) return kc_fail(h, KC_ENOMEM, "driver staging buffers");
+    return KC_OK;
+  }
+  kc_status upload() {
+    if (in.used && hipMemcpyAsync(in.d, in.h, in.used, hipMemcpyHostToDevice, st) != hipSuccess)
       return kc_fail(h, KC_EDEVICE, "upload");
     return KC_OK;
   }
-  kc_status down(void *dst, const DevBuf &b, size_t bytes) {
-    if (bytes && hipMemcpyAsync(dst, b.p, bytes, hipMemcpyDeviceToHost, st) != hipSuccess)
+  kc_status download(const char *what) {
+    if (out.used && hipMemcpyAsync(out.h, out.d, out.used, hipMemcpyDeviceToHost, st) != hipSuccess)
       return kc_fail(h, KC_EDEVICE, "download");
-    return KC_OK;
-  }
-  kc_status alloc(DevBuf &b, size_t bytes) {
-    if (!b.ensure(bytes)) return kc_fail(h, KC_ENOMEM, "driver buffer of %zu bytes", bytes);
-    return KC_OK;
+    return sync(what);
   }
 
   double prune_thr() const { return alpha_ub * (1.0 - o.eps_rel); }
@@ -188,61 +239,128 @@ struct Solver {
     return std::min(lb, alpha_cert);
   }
 
+  // Offsets of a packed node batch (boxes, optional refs) in the input arena.
+  struct BoxPlan {
+    size_t off, lo, hi, roff, ref;
+    int nn, n_refs, max_refs;
+    bool refs;
+  };
+  BoxPlan plan_boxes(const std::vector<const std::vector<float> *> &los,
+                     const std::vector<const Node *> *ref_nodes) {
+    BoxPlan P{};
+    P.nn = (int)los.size();
+    P.off = in.take((size_t)(P.nn + 1) * 4);
+    P.lo = in.take((size_t)P.nn * K * D * 4);
+    P.hi = in.take((size_t)P.nn * K * D * 4);
+    P.refs = false;
+    P.n_refs = 0;
+    P.max_refs = 0;
+    if (ref_nodes) {
+      for (const Node *m : *ref_nodes)
+        for (int k = 0; k < K; ++k) {
+          const int c = m->roff.empty() ? 0 : m->roff[k + 1] - m->roff[k];
+          P.n_refs += c;
+          P.max_refs = std::max(P.max_refs, c);
+        }
+      P.refs = P.n_refs > 0;
+      if (P.refs) {
+        P.roff = in.take((size_t)(P.nn * K + 1) * 4);
+        P.ref = in.take((size_t)P.n_refs * D * 4);
+      }
+    }
+    return P;
+  }
+  void fill_boxes(const BoxPlan &P, const std::vector<const std::vector<float> *> &los,
+                  const std::vector<const std::vector<float> *> &his,
+                  const std::vector<const Node *> *ref_nodes) {
+    int32_t *off = in.hp<int32_t>(P.off);
+    float *lo = in.hp<float>(P.lo), *hi = in.hp<float>(P.hi);
+    for (int i = 0; i < P.nn; ++i) {
+      off[i] = i * K;
+      std::memcpy(lo + (size_t)i * K * D, los[i]->data(), (size_t)K * D * 4);
+      std::memcpy(hi + (size_t)i * K * D, his[i]->data(), (size_t)K * D * 4);
+    }
+    off[P.nn] = P.nn * K;
+    if (P.refs) {
+      int32_t *roff = in.hp<int32_t>(P.roff);
+      float *ref = in.hp<float>(P.ref);
+      int32_t w = 0;
+      for (int i = 0; i < P.nn; ++i) {
+        const Node *m = (*ref_nodes)[i];
+        for (int k = 0; k < K; ++k) {
+          roff[i * K + k] = w;
+          const int c = m->roff.empty() ? 0 : m->roff[k + 1] - m->roff[k];
+          if (c > 0) std::memcpy(ref + (size_t)w * D, m->ref.data() + (size_t)m->roff[k] * D, (size_t)c * D * 4);
+          w += c;
+        }
+      }
+      roff[P.nn * K] = w;
+    }
+  }
+  kc_nodes dev_nodes(const BoxPlan &P) const {
+    return kc_nodes{P.nn, P.nn * K, K, 0, in.dp<int32_t>(P.off), in.dp<float>(P.lo), in.dp<float>(P.hi)};
+  }
+  kc_refs dev_refs(const BoxPlan &P) const {
+    return kc_refs{P.n_refs, P.max_refs, in.dp<int32_t>(P.roff), in.dp<float>(P.ref)};
+  }
+
   // ---------------------------------------------------------------- root --
   kc_status root() {
     // Root region M0 (Section 2.1) as the bounding box of one all-space box.
-    std::vector<float> lo(D, -INFINITY), hi(D, INFINITY);
-    int32_t off[2] = {0, 1};
-    kc_status s = up(d_off, off, sizeof(off));
+    in.reset();
+    out.reset();
+    const size_t o_off = in.take(8), o_lo = in.take(D * 4), o_hi = in.take(D * 4);
+    const size_t o_bl = out.take(D * 4), o_bh = out.take(D * 4), o_am = out.take(D * 4),
+                 o_ax = out.take(D * 4), o_ni = out.take(4), o_na = out.take(4), o_ne = out.take(4);
+    const size_t o_ids = in.take(64 * 8);
+    const size_t o_coords = out.take((size_t)64 * D * 4), o_obj = out.take(8), o_oam = out.take(8);
+    kc_status s = reserve();
     if (s) return s;
-    if ((s = up(d_lo, lo.data(), D * 4)) || (s = up(d_hi, hi.data(), D * 4))) return s;
-    if ((s = alloc(d_bblo, D * 4)) || (s = alloc(d_bbhi, D * 4)) || (s = alloc(d_nin, 4)) ||
-        (s = alloc(d_amin, D * 4)) || (s = alloc(d_amax, D * 4)) || (s = alloc(d_nasg, 4)) ||
-        (s = alloc(d_nexcl, 4)))
-      return s;
-    kc_nodes nd{1, 1, 1, 0, d_off.as<int32_t>(), d_lo.as<float>(), d_hi.as<float>()};
-    s = kc_tighten(h, &act, &nd, INFINITY, nullptr, d_bblo.as<float>(), d_bbhi.as<float>(),
-                   d_nin.as<uint32_t>(), d_amin.as<float>(), d_amax.as<float>(),
-                   d_nasg.as<uint32_t>(), d_nexcl.as<uint32_t>(), nullptr, nullptr, st);
+    int32_t *off = in.hp<int32_t>(o_off);
+    off[0] = 0;
+    off[1] = 1;
+    for (int a = 0; a < D; ++a) {
+      in.hp<float>(o_lo)[a] = -INFINITY;
+      in.hp<float>(o_hi)[a] = INFINITY;
+    }
+    if ((s = upload())) return s;
+    kc_nodes nd{1, 1, 1, 0, in.dp<int32_t>(o_off), in.dp<float>(o_lo), in.dp<float>(o_hi)};
+    s = kc_tighten(h, &act, &nd, INFINITY, nullptr, out.dp<float>(o_bl), out.dp<float>(o_bh),
+                   out.dp<uint32_t>(o_ni), out.dp<float>(o_am), out.dp<float>(o_ax),
+                   out.dp<uint32_t>(o_na), out.dp<uint32_t>(o_ne), nullptr, nullptr, st);
     if (s) return s;
     res->passes++;
-    std::vector<float> bl(D), bh(D);
-    if ((s = down(bl.data(), d_bblo, D * 4)) || (s = down(bh.data(), d_bbhi, D * 4)) ||
-        (s = sync("root box")))
-      return s;
+    if ((s = download("root box"))) return s;
     root_lo.assign(K * D, 0.f);
     root_hi.assign(K * D, 0.f);
     for (int k = 0; k < K; ++k)
       for (int a = 0; a < D; ++a) {
-        root_lo[k * D + a] = bl[a];
-        root_hi[k * D + a] = bh[a];
+        root_lo[k * D + a] = out.hp<float>(o_bl)[a];
+        root_hi[k * D + a] = out.hp<float>(o_bh)[a];
       }
 
     // Farthest first traversal (Algorithm 2), distances in float64.
     std::vector<int64_t> T(K);
     T[0] = o.fft_start;
-    if ((s = alloc(d_ids, 64 * 8)) || (s = alloc(d_coords, 64 * D * 4)) ||
-        (s = alloc(d_orig, 64 * 8)) || (s = alloc(d_obj, 8)) || (s = alloc(d_oam, 8)))
-      return s;
     for (int j = 1; j <= K; ++j) {
-      if ((s = up(d_ids, T.data(), j * 8))) return s;
-      if ((s = kc_gather(h, &act, d_ids.as<int64_t>(), j, nullptr, d_coords.as<float>(), nullptr, st)))
+      std::memcpy(in.hp<int64_t>(o_ids), T.data(), (size_t)j * 8);
+      if (hipMemcpyAsync(in.dp<int64_t>(o_ids), in.hp<int64_t>(o_ids), (size_t)j * 8,
+                         hipMemcpyHostToDevice, st) != hipSuccess)
+        return kc_fail(h, KC_EDEVICE, "upload");
+      if ((s = kc_gather(h, &act, in.dp<int64_t>(o_ids), j, nullptr, out.dp<float>(o_coords), nullptr, st)))
         return s;
-      s = kc_objective(h, &act, 1, j, d_coords.as<float>(), 64, d_obj.as<double>(),
-                       d_oam.as<int64_t>(), st);
+      s = kc_objective(h, &act, 1, j, out.dp<float>(o_coords), 64, out.dp<double>(o_obj),
+                       out.dp<int64_t>(o_oam), st);
       if (s) return s;
       res->passes++;
-      double ob;
-      int64_t am;
-      if ((s = down(&ob, d_obj, 8)) || (s = down(&am, d_oam, 8)) || (s = sync("fft"))) return s;
+      if ((s = download("fft"))) return s;
       if (j < K)
-        T[j] = am;
+        T[j] = *out.hp<int64_t>(o_oam);
       else
-        alpha_cert = ob;
+        alpha_cert = *out.hp<double>(o_obj);
     }
     inc_ids = T;
-    inc_coords.resize(K * D);
-    if ((s = down(inc_coords.data(), d_coords, K * D * 4)) || (s = sync("fft centers"))) return s;
+    inc_coords.assign(out.hp<float>(o_coords), out.hp<float>(o_coords) + K * D);
     alpha_ub = alpha_cert;
     res->fft_obj = alpha_cert;
 
@@ -263,7 +381,6 @@ struct Solver {
           }
         }
     }
-    if (seeds) seed_coords = inc_coords;
     symmetry = !seeds && o.use_bt;
     res->seeds_found = seeds;
 
@@ -276,7 +393,7 @@ struct Solver {
     r->roff.assign(K + 1, 0);
     if (seeds) {
       for (int k = 0; k <= K; ++k) r->roff[k] = k;
-      r->ref = seed_coords;
+      r->ref = inc_coords;
       r->rid = inc_ids;
     }
     if (symmetry) apply_symmetry(r->lo, r->hi);
@@ -327,171 +444,101 @@ struct Solver {
     return true;
   }
 
-  kc_status upload_nodes(const std::vector<const std::vector<float> *> &los,
-                         const std::vector<const std::vector<float> *> &his, kc_nodes *nd) {
-    const int nn = (int)los.size();
-    std::vector<int32_t> off(nn + 1);
-    std::vector<float> lo((size_t)nn * K * D), hi((size_t)nn * K * D);
-    for (int i = 0; i < nn; ++i) {
-      off[i] = i * K;
-      std::memcpy(&lo[(size_t)i * K * D], los[i]->data(), K * D * 4);
-      std::memcpy(&hi[(size_t)i * K * D], his[i]->data(), K * D * 4);
-    }
-    off[nn] = nn * K;
-    kc_status s;
-    if ((s = up(d_off, off.data(), off.size() * 4)) || (s = up(d_lo, lo.data(), lo.size() * 4)) ||
-        (s = up(d_hi, hi.data(), hi.size() * 4)))
-      return s;
-    *nd = kc_nodes{nn, nn * K, K, 0, d_off.as<int32_t>(), d_lo.as<float>(), d_hi.as<float>()};
-    return KC_OK;
-  }
-
-  // Box k of node i gets the refs of cluster k of node i. Returns false (and
-  // uploads nothing) when no node has any ref.
-  kc_status upload_refs(const std::vector<const Node *> &ns, kc_refs *rf, bool *any) {
-    const int nn = (int)ns.size();
-    std::vector<int32_t> roff(nn * K + 1);
-    std::vector<float> ref;
-    int mx = 0;
-    int32_t w = 0;
-    for (int i = 0; i < nn; ++i)
-      for (int k = 0; k < K; ++k) {
-        roff[i * K + k] = w;
-        const Node *m = ns[i];
-        const int c = m->roff.empty() ? 0 : m->roff[k + 1] - m->roff[k];
-        if (c > 0) ref.insert(ref.end(), m->ref.begin() + (size_t)m->roff[k] * D,
-                              m->ref.begin() + (size_t)m->roff[k + 1] * D);
-        w += c;
-        mx = std::max(mx, c);
-      }
-    roff[nn * K] = w;
-    *any = w > 0;
-    if (!*any) return KC_OK;
-    kc_status s;
-    if ((s = up(d_roff, roff.data(), roff.size() * 4)) || (s = up(d_ref, ref.data(), ref.size() * 4)))
-      return s;
-    *rf = kc_refs{w, mx, d_roff.as<int32_t>(), d_ref.as<float>()};
-    return KC_OK;
-  }
-
   // ------------------------------------------------------------ tighten --
-  // Returns, per node, whether it survived, and replaces its boxes by M-hat.
   struct TAgg {
-    std::vector<float> bbl, bbh, amn, amx;
-    std::vector<uint32_t> nin, nasg, nex;
+    std::vector<uint32_t> nin, nasg;
   } ta;
 
+  // Tightens every node of the batch in place (M-hat of Algorithm 4) and
+  // records the refs it found for the node's children; alive[i] = 0 when the
+  // node holds no solution of objective <= a_bt.
   kc_status tighten(std::vector<Node *> &batch, std::vector<char> &alive, double a_bt) {
     const int nn = (int)batch.size();
     std::vector<const std::vector<float> *> los(nn), his(nn);
+    std::vector<const Node *> cn(batch.begin(), batch.end());
     for (int i = 0; i < nn; ++i) {
       los[i] = &batch[i]->lo;
       his[i] = &batch[i]->hi;
     }
-    kc_nodes nd;
-    kc_refs rf;
-    kc_status s = upload_nodes(los, his, &nd);
-    if (s) return s;
-    bool wr = false;
-    if (o.use_bt) {
-      std::vector<const Node *> cn(batch.begin(), batch.end());
-      if ((s = upload_refs(cn, &rf, &wr))) return s;
-    }
+    const bool want_far = o.use_bt && o.max_refs > 0;
+    in.reset();
+    out.reset();
+    const BoxPlan P = plan_boxes(los, o.use_bt ? &cn : nullptr);
     const size_t nbd = (size_t)nn * K * D, nb = (size_t)nn * K;
-    if ((s = alloc(d_bblo, nbd * 4)) || (s = alloc(d_bbhi, nbd * 4)) || (s = alloc(d_amin, nbd * 4)) ||
-        (s = alloc(d_amax, nbd * 4)) || (s = alloc(d_nin, nb * 4)) || (s = alloc(d_nasg, nb * 4)) ||
-        (s = alloc(d_nexcl, nn * 4)) || (s = alloc(d_far, nb * 8)))
-      return s;
-    s = kc_tighten(h, &act, &nd, a_bt, wr ? &rf : nullptr, d_bblo.as<float>(), d_bbhi.as<float>(),
-                   d_nin.as<uint32_t>(), d_amin.as<float>(), d_amax.as<float>(),
-                   d_nasg.as<uint32_t>(), d_nexcl.as<uint32_t>(),
-                   o.use_bt && o.max_refs > 0 ? d_far.as<int64_t>() : nullptr, nullptr, st);
+    const size_t o_bl = out.take(nbd * 4), o_bh = out.take(nbd * 4), o_am = out.take(nbd * 4),
+                 o_ax = out.take(nbd * 4), o_ni = out.take(nb * 4), o_na = out.take(nb * 4),
+                 o_ne = out.take((size_t)nn * 4), o_far = out.take(nb * 8),
+                 o_fc = out.take(nb * D * 4), o_fo = out.take(nb * 8);
+    kc_status s = reserve();
+    if (s) return s;
+    fill_boxes(P, los, his, o.use_bt ? &cn : nullptr);
+    if ((s = upload())) return s;
+    const kc_nodes nd = dev_nodes(P);
+    const kc_refs rf = dev_refs(P);
+    s = kc_tighten(h, &act, &nd, a_bt, P.refs ? &rf : nullptr, out.dp<float>(o_bl), out.dp<float>(o_bh),
+                   out.dp<uint32_t>(o_ni), out.dp<float>(o_am), out.dp<float>(o_ax),
+                   out.dp<uint32_t>(o_na), out.dp<uint32_t>(o_ne),
+                   want_far ? out.dp<int64_t>(o_far) : nullptr, nullptr, st);
     if (s) return s;
     res->passes++;
-    ta.bbl.resize(nbd);
-    ta.bbh.resize(nbd);
-    ta.amn.resize(nbd);
-    ta.amx.resize(nbd);
-    ta.nin.resize(nb);
-    ta.nasg.resize(nb);
-    ta.nex.resize(nn);
-    if ((s = down(ta.bbl.data(), d_bblo, nbd * 4)) || (s = down(ta.bbh.data(), d_bbhi, nbd * 4)) ||
-        (s = down(ta.amn.data(), d_amin, nbd * 4)) || (s = down(ta.amx.data(), d_amax, nbd * 4)) ||
-        (s = down(ta.nin.data(), d_nin, nb * 4)) || (s = down(ta.nasg.data(), d_nasg, nb * 4)) ||
-        (s = down(ta.nex.data(), d_nexcl, nn * 4)))
+    // coordinates and original ids of the new refs, gathered before any
+    // sample reduction moves the active samples
+    if (want_far &&
+        (s = kc_gather(h, &act, out.dp<int64_t>(o_far), (int)nb, idx, out.dp<float>(o_fc),
+                       out.dp<int64_t>(o_fo), st)))
       return s;
-    std::vector<int64_t> far(nb, -1);
-    const bool want_far = o.use_bt && o.max_refs > 0;
-    if (want_far && (s = down(far.data(), d_far, nb * 8))) return s;
-    if ((s = sync("tighten"))) return s;
-    if (want_far) {
-      // coordinates and original ids of the new refs, gathered before any
-      // sample reduction moves the active samples
-      std::vector<int64_t> ids;
-      for (size_t b = 0; b < nb; ++b)
-        if (far[b] >= 0) ids.push_back(far[b]);
-      std::vector<float> coords(ids.size() * D);
-      std::vector<int64_t> orig(ids.size());
-      if (!ids.empty()) {
-        if ((s = up(d_ids, ids.data(), ids.size() * 8)) || (s = alloc(d_coords, ids.size() * D * 4)) ||
-            (s = alloc(d_orig, ids.size() * 8)))
-          return s;
-        if ((s = kc_gather(h, &act, d_ids.as<int64_t>(), (int)ids.size(), idx, d_coords.as<float>(),
-                           d_orig.as<int64_t>(), st)))
-          return s;
-        if ((s = down(coords.data(), d_coords, coords.size() * 4)) ||
-            (s = down(orig.data(), d_orig, orig.size() * 8)) || (s = sync("new refs")))
-          return s;
-      }
-      size_t q = 0;
-      for (int i = 0; i < nn; ++i) {
-        Node *m = batch[i];
-        m->new_ref.assign((size_t)K * D, 0.f);
-        m->new_rid.assign(K, -1);
-        for (int k = 0; k < K; ++k)
-          if (far[(size_t)i * K + k] >= 0) {
-            std::memcpy(&m->new_ref[(size_t)k * D], &coords[q * D], D * 4);
-            m->new_rid[k] = orig[q];
-            ++q;
-          }
-      }
-    }
+    if ((s = download("tighten"))) return s;
+
+    const float *bbl = out.hp<float>(o_bl), *bbh = out.hp<float>(o_bh);
+    const float *amn = out.hp<float>(o_am), *amx = out.hp<float>(o_ax);
+    const uint32_t *nin = out.hp<uint32_t>(o_ni), *nasg = out.hp<uint32_t>(o_na);
+    const uint32_t *nex = out.hp<uint32_t>(o_ne);
+    const int64_t *far = out.hp<int64_t>(o_far);
+    const float *fc = out.hp<float>(o_fc);
+    const int64_t *fo = out.hp<int64_t>(o_fo);
+    ta.nin.assign(nin, nin + nb);
+    ta.nasg.assign(nasg, nasg + nb);
 
     const double sa = o.use_bt ? std::sqrt(a_bt) * (1.0 + 0x1p-50) : INFINITY;
     alive.assign(nn, 1);
     for (int i = 0; i < nn; ++i) {
       Node *m = batch[i];
-      bool ok = ta.nex[i] == 0;
+      if (want_far) {
+        m->new_ref.assign((size_t)K * D, 0.f);
+        m->new_rid.assign(K, -1);
+        for (int k = 0; k < K; ++k) {
+          const size_t b = (size_t)i * K + k;
+          if (far[b] >= 0) {
+            std::memcpy(&m->new_ref[(size_t)k * D], fc + b * D, (size_t)D * 4);
+            m->new_rid[k] = fo[b];
+          }
+        }
+      }
+      bool ok = nex[i] == 0;
       for (int k = 0; k < K && ok; ++k) {
         const size_t b = (size_t)i * K + k;
-        if (ta.nin[b] == 0) {
+        if (nin[b] == 0) {
           ok = false;
           break;
         }
         for (int a = 0; a < D; ++a) {
           const size_t q = b * D + a;
-          float L = std::max(m->lo[k * D + a], ta.bbl[q]);
-          float H = std::min(m->hi[k * D + a], ta.bbh[q]);
+          float L = std::max(m->lo[k * D + a], bbl[q]);
+          float H = std::min(m->hi[k * D + a], bbh[q]);
           if (o.use_bt && std::isfinite(sa)) {
-            // box-based tightening with the assigned samples and the seed
+            // box-based tightening with the assigned samples and the refs
             double amax = -INFINITY, amin = INFINITY;
-            if (ta.nasg[b] > 0) {
-              amax = ta.amx[q];
-              amin = ta.amn[q];
+            if (nasg[b] > 0) {
+              amax = amx[q];
+              amin = amn[q];
             }
             if (!m->roff.empty())
               for (int r = m->roff[k]; r < m->roff[k + 1]; ++r) {
                 amax = std::max(amax, (double)m->ref[(size_t)r * D + a]);
                 amin = std::min(amin, (double)m->ref[(size_t)r * D + a]);
               }
-            if (std::isfinite(amax)) {
-              const double v = nextafter(amax - sa, -INFINITY);
-              L = std::max(L, kc_round_up_f32(v));
-            }
-            if (std::isfinite(amin)) {
-              const double v = nextafter(amin + sa, INFINITY);
-              H = std::min(H, kc_round_down_f32(v));
-            }
+            if (std::isfinite(amax)) L = std::max(L, kc_round_up_f32(nextafter(amax - sa, -INFINITY)));
+            if (std::isfinite(amin)) H = std::min(H, kc_round_down_f32(nextafter(amin + sa, INFINITY)));
           }
           if (!(L <= H)) ok = false;
           m->lo[k * D + a] = L;
@@ -499,7 +546,6 @@ struct Solver {
         }
       }
       if (ok && symmetry) ok = apply_symmetry(m->lo, m->hi);
-      // an infeasible node holds no solution of objective <= a_bt
       alive[i] = ok;
     }
     return KC_OK;
@@ -525,23 +571,26 @@ struct Solver {
       beta = std::min(beta, m->lb);
     }
     if (los.empty()) return KC_OK;
-    kc_nodes nd;
-    kc_refs rf;
-    bool wr = false;
-    kc_status s = upload_nodes(los, his, &nd);
+    in.reset();
+    out.reset();
+    const BoxPlan P = plan_boxes(los, o.use_bt ? &ns : nullptr);
+    const size_t o_n = out.take(8);
+    kc_status s = reserve();
     if (s) return s;
-    if (o.use_bt && (s = upload_refs(ns, &rf, &wr))) return s;
+    fill_boxes(P, los, his, o.use_bt ? &ns : nullptr);
+    if ((s = upload())) return s;
     const int nxt = cur == 0 ? 1 : 0;
     const size_t bytes = (size_t)D * X0->ld * 4;
     if (!xbuf[nxt].ensure(bytes) || !ibuf[nxt].ensure((size_t)X0->ld * 4))
       return kc_fail(h, KC_ENOMEM, "sample buffers");
-    if ((s = alloc(d_obj, 8))) return s;
-    s = kc_reduce(h, &act, idx, &nd, wr ? &rf : nullptr, beta, alpha_ub, nullptr,
-                  xbuf[nxt].as<float>(), ibuf[nxt].as<uint32_t>(), X0->ld, d_obj.as<int64_t>(), st);
+    const kc_nodes nd = dev_nodes(P);
+    const kc_refs rf = dev_refs(P);
+    s = kc_reduce(h, &act, idx, &nd, P.refs ? &rf : nullptr, beta, alpha_ub, nullptr,
+                  xbuf[nxt].as<float>(), ibuf[nxt].as<uint32_t>(), X0->ld, out.dp<int64_t>(o_n), st);
     if (s) return s;
     res->passes++;
-    int64_t n_out = 0;
-    if ((s = down(&n_out, d_obj, 8)) || (s = sync("reduce"))) return s;
+    if ((s = download("reduce"))) return s;
+    const int64_t n_out = *out.hp<int64_t>(o_n);
     if (n_out < 1) return KC_OK;  // keep the previous set (nothing left to bound)
     cur = nxt;
     act.x = xbuf[cur].as<float>();
@@ -666,28 +715,34 @@ struct Solver {
         }
     }
     if (o.branching != 1 || !o.mlp_w) return KC_OK;
-    std::vector<float> feat;
     std::vector<int> row_node, row_q;
     for (int i = 0; i < nn; ++i) {
       const Node *m = nodes[i];
-      for (int k = 0; k < K; ++k)
-        for (int a = 0; a < D; ++a) {
-          if (!((double)m->hi[k * D + a] - m->lo[k * D + a] > 0)) continue;
-          feat.resize(feat.size() + NFEAT);
-          features(m, bidx[i], (int)nodes.size(), &ta.nin[(size_t)bidx[i] * K],
-                   &ta.nasg[(size_t)bidx[i] * K], k, a, &feat[feat.size() - NFEAT]);
+      for (int q = 0; q < K * D; ++q)
+        if ((double)m->hi[q] - m->lo[q] > 0) {
           row_node.push_back(i);
-          row_q.push_back(k * D + a);
+          row_q.push_back(q);
         }
     }
     const int64_t rows = (int64_t)row_node.size();
     if (rows == 0) return KC_OK;
-    kc_status s;
-    if ((s = up(d_feat, feat.data(), feat.size() * 4)) || (s = alloc(d_score, rows * 4))) return s;
-    s = kc_mlp_forward(h, o.mlp_w, d_feat.as<float>(), rows, d_score.as<float>(), nullptr, st);
+    in.reset();
+    out.reset();
+    const size_t o_f = in.take((size_t)rows * NFEAT * 4);
+    const size_t o_s = out.take((size_t)rows * 4);
+    kc_status s = reserve();
     if (s) return s;
-    std::vector<float> sc(rows);
-    if ((s = down(sc.data(), d_score, rows * 4)) || (s = sync("branching network"))) return s;
+    float *feat = in.hp<float>(o_f);
+    for (int64_t r = 0; r < rows; ++r) {
+      const int i = row_node[r];
+      features(nodes[i], bidx[i], nn, &ta.nin[(size_t)bidx[i] * K], &ta.nasg[(size_t)bidx[i] * K],
+               row_q[r] / D, row_q[r] % D, feat + r * NFEAT);
+    }
+    if ((s = upload())) return s;
+    s = kc_mlp_forward(h, o.mlp_w, in.dp<float>(o_f), rows, out.dp<float>(o_s), nullptr, st);
+    if (s) return s;
+    if ((s = download("branching network"))) return s;
+    const float *sc = out.hp<float>(o_s);
     std::vector<float> best(nn, -INFINITY);
     for (int64_t r = 0; r < rows; ++r) {
       const int i = row_node[r];
@@ -732,18 +787,21 @@ struct Solver {
       los.push_back(&clo[c]);
       his.push_back(&chi[c]);
     }
-    kc_nodes nd;
-    kc_status s = upload_nodes(los, his, &nd);
-    if (s) return s;
     const int ne = (int)los.size();
-    if ((s = alloc(d_lbsafe, ne * 8)) || (s = alloc(d_cand, (size_t)ne * K * 8))) return s;
-    s = kc_lower_bound(h, &act, &nd, nullptr, d_lbsafe.as<double>(), nullptr, d_cand.as<int64_t>(), st);
+    in.reset();
+    out.reset();
+    const BoxPlan P = plan_boxes(los, nullptr);
+    const size_t o_lb = out.take((size_t)ne * 8), o_c = out.take((size_t)ne * K * 8);
+    kc_status s = reserve();
     if (s) return s;
-    std::vector<double> lb(ne);
-    std::vector<int64_t> cand((size_t)ne * K);
-    if ((s = down(lb.data(), d_lbsafe, ne * 8)) || (s = down(cand.data(), d_cand, cand.size() * 8)) ||
-        (s = sync("strong branching")))
-      return s;
+    fill_boxes(P, los, his, nullptr);
+    if ((s = upload())) return s;
+    const kc_nodes nd = dev_nodes(P);
+    s = kc_lower_bound(h, &act, &nd, nullptr, out.dp<double>(o_lb), nullptr, out.dp<int64_t>(o_c), st);
+    if (s) return s;
+    if ((s = download("strong branching"))) return s;
+    const double *lb = out.hp<double>(o_lb);
+    const int64_t *cand = out.hp<int64_t>(o_c);
     const double al = alpha_ub;
     const double e = 1e-6 * al;
     int last = -1;
@@ -809,7 +867,9 @@ struct Solver {
 
       // bounds tightening
       const double a_bt = o.use_bt ? alpha_ub : INFINITY;
+      double tp = now_s();
       if ((s = tighten(batch, alive, a_bt))) return s;
+      t_tighten += now_s() - tp;
       std::vector<Node *> live;
       std::vector<int> bidx;
       for (size_t i = 0; i < batch.size(); ++i) {
@@ -821,12 +881,24 @@ struct Solver {
           delete batch[i];
         }
       }
-      // sample reduction every i_sr passes, over the open nodes and this batch
+      // sample reduction every i_sr passes, over the open nodes and this
+      // batch; the interval doubles (up to 64 i_sr) while reductions delete
+      // under 1% of the active samples and resets when one deletes more
       ++passes_since_sr;
-      if (o.i_sr > 0 && passes_since_sr >= o.i_sr) {
+      if (o.i_sr > 0 && sr_interval == 0) sr_interval = o.i_sr;
+      if (o.i_sr > 0 && passes_since_sr >= sr_interval) {
         passes_since_sr = 0;
+        tp = now_s();
+        const int64_t before = act.n;
         if ((s = reduce(live))) return s;
+        ++sr_runs;
+        if ((double)(before - act.n) < 0.01 * (double)before)
+          sr_interval = std::min<int64_t>(sr_interval * 2, (int64_t)o.i_sr * 64);
+        else
+          sr_interval = o.i_sr;
+        t_reduce += now_s() - tp;
       }
+      tp = now_s();
 
       // branching; a node whose boxes are all single points is a leaf
       std::vector<Node *> to_branch, leaves;
@@ -899,8 +971,11 @@ struct Solver {
         ev.push_back(m);
         is_leaf.push_back(1);
       }
+      t_branch += now_s() - tp;
+      tp = now_s();
       if (!ev.empty())
         if ((s = bound(ev, is_leaf))) return s;
+      t_bound += now_s() - tp;
 
       if (!heap.empty()) {
         const double lb = global_lb();
@@ -911,12 +986,18 @@ struct Solver {
                 (long long)res->nodes, heap.size(), (long long)act.n, alpha_cert, global_lb(),
                 now_s() - t0);
     }
+    if (o.verbose)
+      fprintf(stderr,
+              "[kc_solve] phases: tighten %.3fs reduce %.3fs (%lld runs) branch %.3fs bound %.3fs "
+              "total %.3fs\n",
+              t_tighten, t_reduce, (long long)sr_runs, t_branch, t_bound, now_s() - t0);
     return KC_OK;
   }
 
   // Bounds every node of `ev`: lower bound + candidates in one launch, the
-  // candidates' objective in one float32 launch, float64 certificate of an
-  // improvement. Children with an empty box are dropped; leaves leave the tree.
+  // candidates' objective in one float32 launch (coordinates gathered on the
+  // device), float64 certificate of an improvement. Children with an empty
+  // box are dropped; leaves leave the tree.
   kc_status bound(std::vector<Node *> &ev, const std::vector<char> &is_leaf) {
     const int ne = (int)ev.size();
     std::vector<const std::vector<float> *> los(ne), his(ne);
@@ -924,98 +1005,87 @@ struct Solver {
       los[i] = &ev[i]->lo;
       his[i] = &ev[i]->hi;
     }
-    kc_nodes nd;
-    kc_status s = upload_nodes(los, his, &nd);
+    in.reset();
+    out.reset();
+    const BoxPlan P = plan_boxes(los, nullptr);
+    const size_t ng = (size_t)ne * K + ne;  // candidates, then the LB samples
+    const size_t o_lb = out.take((size_t)ne * 8), o_ids = out.take(ng * 8),
+                 o_xy = out.take(ng * D * 4), o_orig = out.take(ng * 8),
+                 o_obj = out.take((size_t)ne * 8), o_oam = out.take((size_t)ne * 8),
+                 o_cert = out.take(8), o_cam = out.take(8);
+    kc_status s = reserve();
     if (s) return s;
-    if ((s = alloc(d_lbraw, ne * 4)) || (s = alloc(d_lbsafe, ne * 8)) || (s = alloc(d_argmax, ne * 8)) ||
-        (s = alloc(d_cand, (size_t)ne * K * 8)))
-      return s;
+    fill_boxes(P, los, his, nullptr);
+    if ((s = upload())) return s;
+    const kc_nodes nd = dev_nodes(P);
+    int64_t *ids = out.dp<int64_t>(o_ids);
     (void)hipEventRecord(h->ev0, st);
-    s = kc_lower_bound(h, &act, &nd, d_lbraw.as<float>(), d_lbsafe.as<double>(), d_argmax.as<int64_t>(),
-                       d_cand.as<int64_t>(), st);
+    s = kc_lower_bound(h, &act, &nd, nullptr, out.dp<double>(o_lb), ids + (size_t)ne * K, ids, st);
     (void)hipEventRecord(h->ev1, st);
     if (s) return s;
     res->passes++;
     res->evals += act.n * (int64_t)ne * K;
-    std::vector<double> lb(ne);
-    std::vector<int64_t> am(ne), cand((size_t)ne * K);
-    if ((s = down(lb.data(), d_lbsafe, ne * 8)) || (s = down(am.data(), d_argmax, ne * 8)) ||
-        (s = down(cand.data(), d_cand, cand.size() * 8)) || (s = sync("lower bound")))
+    if ((s = kc_gather(h, &act, ids, (int)ng, idx, out.dp<float>(o_xy), out.dp<int64_t>(o_orig), st)))
       return s;
+    // the objective of every candidate set (a set with an empty box reads
+    // sample 0 in its place; its value is never used)
+    s = kc_objective(h, &act, ne, K, out.dp<float>(o_xy), 32, out.dp<double>(o_obj),
+                     out.dp<int64_t>(o_oam), st);
+    if (s) return s;
+    res->passes++;
+    if ((s = download("bound"))) return s;
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, h->ev0, h->ev1);
     res->lb_kernel_ms += ms;
+    const double *lb = out.hp<double>(o_lb);
+    const int64_t *cand = out.hp<int64_t>(o_ids);
+    const float *xy = out.hp<float>(o_xy);
+    const int64_t *orig = out.hp<int64_t>(o_orig);
+    const double *ub = out.hp<double>(o_obj);
 
-    // candidate sets of the nodes whose boxes all hold a sample
-    std::vector<int> keep;
-    std::vector<int64_t> ids;
-    for (int i = 0; i < ne; ++i) {
-      bool empty = false;
-      for (int k = 0; k < K; ++k)
-        if (cand[(size_t)i * K + k] < 0) empty = true;
-      if (empty) {
-        // no sample in some box: the node holds no feasible centers
-        delete ev[i];
-        ev[i] = nullptr;
-        continue;
-      }
-      keep.push_back(i);
-      for (int k = 0; k < K; ++k) ids.push_back(cand[(size_t)i * K + k]);
-    }
-    const int C = (int)keep.size();
-    for (int i : keep) ids.push_back(am[i]);  // LB samples, for the features
-    const int ng = (int)ids.size();
-    if (C == 0) return KC_OK;
-    if ((s = up(d_ids, ids.data(), ids.size() * 8)) || (s = alloc(d_coords, (size_t)ng * D * 4)) ||
-        (s = alloc(d_orig, (size_t)ng * 8)) || (s = alloc(d_obj, (size_t)C * 8)) ||
-        (s = alloc(d_oam, (size_t)C * 8)))
-      return s;
-    if ((s = kc_gather(h, &act, d_ids.as<int64_t>(), ng, idx, d_coords.as<float>(), d_orig.as<int64_t>(), st)))
-      return s;
-    s = kc_objective(h, &act, C, K, d_coords.as<float>(), 32, d_obj.as<double>(), d_oam.as<int64_t>(), st);
-    if (s) return s;
-    res->passes++;
-    std::vector<double> ub(C);
-    std::vector<float> coords((size_t)ng * D);
-    std::vector<int64_t> orig(ng);
-    if ((s = down(ub.data(), d_obj, C * 8)) || (s = down(coords.data(), d_coords, coords.size() * 4)) ||
-        (s = down(orig.data(), d_orig, orig.size() * 8)) || (s = sync("objective")))
-      return s;
+    std::vector<char> ok(ne, 1);
     int best = -1;
-    for (int c = 0; c < C; ++c)
-      if (ub[c] < alpha_ub && (best < 0 || ub[c] < ub[best])) best = c;
+    for (int i = 0; i < ne; ++i) {
+      for (int k = 0; k < K; ++k)
+        if (cand[(size_t)i * K + k] < 0) ok[i] = 0;  // no sample in some box
+      if (ok[i] && ub[i] < alpha_ub && (best < 0 || ub[i] < ub[best])) best = i;
+    }
     if (best >= 0) {
       alpha_ub = ub[best];
       // certify in float64 over the original samples
-      if ((s = kc_objective(h, X0, 1, K, d_coords.as<float>() + (size_t)best * K * D, 64,
-                            d_obj.as<double>(), d_oam.as<int64_t>(), st)))
+      if ((s = kc_objective(h, X0, 1, K, out.dp<float>(o_xy) + (size_t)best * K * D, 64,
+                            out.dp<double>(o_cert), out.dp<int64_t>(o_cam), st)))
         return s;
       res->passes++;
-      double cert;
-      if ((s = down(&cert, d_obj, 8)) || (s = sync("certificate"))) return s;
+      double cert = 0.0;
+      if (hipMemcpyAsync(&cert, out.dp<double>(o_cert), 8, hipMemcpyDeviceToHost, st) != hipSuccess)
+        return kc_fail(h, KC_EDEVICE, "download");
+      if ((s = sync("certificate"))) return s;
       if (cert < alpha_cert) {
         alpha_cert = cert;
-        inc_ids.assign(orig.begin() + (size_t)best * K, orig.begin() + (size_t)best * K + K);
-        inc_coords.assign(coords.begin() + (size_t)best * K * D, coords.begin() + (size_t)best * K * D + K * D);
+        inc_ids.assign(orig + (size_t)best * K, orig + (size_t)best * K + K);
+        inc_coords.assign(xy + (size_t)best * K * D, xy + (size_t)best * K * D + K * D);
       }
       alpha_ub = std::min(alpha_ub, alpha_cert);
     }
     const double thr = prune_thr();
-    const int d = D;
-    for (int c = 0; c < C; ++c) {
-      const int i = keep[c];
+    const double rel = kc_rel_margin(D) + 0x1p-50, eta = kc_abs_margin(D);
+    for (int i = 0; i < ne; ++i) {
       Node *m = ev[i];
+      if (!ok[i]) {
+        delete m;  // the node holds no feasible centers
+        continue;
+      }
       m->lb = std::max(m->lb, lb[i]);
-      for (int a = 0; a < D; ++a) m->xstar[a] = coords[((size_t)C * K + c) * D + a];
+      std::memcpy(m->xstar, xy + ((size_t)ne * K + i) * D, (size_t)D * 4);
       if (!is_leaf[i] && m->split_k >= 0) {
         const int q = m->split_k * D + m->split_a;
         pc_sum[m->side][q] += (m->lb - m->parent_lb) / (alpha_ub > 0 ? alpha_ub : 1.0);
         pc_cnt[m->side][q]++;
       }
       if (is_leaf[i]) {
-        // every box is one point: the node's only solution has objective ub[c]
-        const double lo_obj = std::max(0.0, (ub[c] - kc_abs_margin(d)) / (1.0 + kc_rel_margin(d) + 0x1p-50) *
-                                                (1.0 - kc_rel_margin(d) - 0x1p-50) - kc_abs_margin(d));
+        // every box is one point: the node's only solution has objective ub[i]
+        const double lo_obj = std::max(0.0, (ub[i] - eta) / (1.0 + rel) * (1.0 - rel) - eta);
         lb_closed = std::min(lb_closed, std::max(m->lb, lo_obj));
         delete m;
       } else if (m->lb >= thr) {
@@ -1024,7 +1094,6 @@ struct Solver {
       } else {
         heap_push(m);
       }
-      ev[i] = nullptr;
     }
     return KC_OK;
   }
@@ -1044,7 +1113,10 @@ extern "C" kc_status kc_solve(kc_handle *h, const kc_points *pts, const kc_opts 
   KC_RETURN_IF(opts->fft_start < 0 || opts->fft_start >= pts->n, h, KC_EINVAL,
                "fft_start out of range");
   KC_RETURN_IF(!(opts->eps_rel >= 0.0 && opts->eps_rel < 1.0), h, KC_EINVAL, "eps_rel in [0,1)");
+  KC_RETURN_IF(opts->max_refs < 0 || opts->max_refs > 64, h, KC_EINVAL, "max_refs in [0,64]");
   KC_RETURN_IF(opts->branching == 1 && !opts->mlp_w, h, KC_EINVAL, "learned branching needs mlp_w");
+  KC_RETURN_IF(opts->sb_every > 0 && (!opts->sb_feat || !opts->sb_score || !opts->sb_node || opts->sb_cap < 1),
+               h, KC_EINVAL, "strong-branching labels need their host arrays");
   std::memset(res, 0, sizeof(*res));
   Solver S(h, pts, opts, res);
   const double t0 = now_s();

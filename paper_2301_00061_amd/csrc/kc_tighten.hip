@@ -233,16 +233,22 @@ __global__ __launch_bounds__(WG) void k_tighten(TightenArgs A) {
 
       // Sample-based assignment (Lemma 2), only for unassigned samples.
       if (label == -1 && allref) {
-        int n_farc = 0, rest_k = -1;
-        for (int k = 0; k < cnt; ++k) {
+        // cluster k is excluded once one of its refs is farther than 4 alpha;
+        // the scan stops when two clusters remain possible
+        int n_near = 0, rest_k = -1;
+        for (int k = 0; k < cnt && n_near < 2; ++k) {
           bool fr = false;
-          for (int r = 0; r < s_rcnt[k]; ++r) fr = fr || (sqdist(xv, rf + (s_rbeg[k] + r) * DM, dd, DM) > A.t_sample);
-          if (fr)
-            ++n_farc;
-          else
+          for (int r = 0; r < s_rcnt[k]; ++r)
+            if (sqdist(xv, rf + (s_rbeg[k] + r) * DM, dd, DM) > A.t_sample) {
+              fr = true;
+              break;
+            }
+          if (!fr) {
+            ++n_near;
             rest_k = k;
+          }
         }
-        if (n_farc == cnt - 1) label = rest_k;
+        if (n_near == 1) label = rest_k;
       }
       if (write_labels) A.labels[sid] = (int8_t)label;
       nex += (label == -2);
@@ -267,7 +273,11 @@ __global__ __launch_bounds__(WG) void k_tighten(TightenArgs A) {
           // S_+^k: inside box k and within the ball of every ref of box k.
           bool in = (inmask >> (single ? k : kk)) & 1u;
           if (in)
-            for (int r = 0; r < s_rcnt[k]; ++r) in = in && (sqdist(xv, rf + (s_rbeg[k] + r) * DM, dd, DM) <= A.t_ball);
+            for (int r = 0; r < s_rcnt[k]; ++r)
+              if (!(sqdist(xv, rf + (s_rbeg[k] + r) * DM, dd, DM) <= A.t_ball)) {
+                in = false;
+                break;
+              }
           if (in) {
             ++nin[kk];
 #pragma unroll
