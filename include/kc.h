@@ -226,8 +226,10 @@ typedef struct {
   int32_t verbose;      /* 1: progress lines on stderr                      */
   /* Strong-branching labels (training data of the branching network): the
    * first sb_first branched nodes and every sb_every-th after them get every
-   * positive-width candidate (cluster, attribute) split and bounded; one row
-   * per candidate is written to the host arrays below (capacity sb_cap). */
+   * candidate (cluster, attribute) split and bounded; one row per candidate is
+   * written to the host arrays below (capacity sb_cap). Candidates, for the
+   * labels and for the learned rule, are the sides at least half as wide as
+   * the node's widest side. */
   int32_t sb_first;
   int32_t sb_every;     /* 0 = no labels                                    */
   int32_t sb_cap;

@@ -35,6 +35,11 @@
 namespace {
 
 constexpr int NFEAT = 32;
+// The learned rule and the strong-branching labels consider only the sides at
+// least this fraction of the node's widest side: every split still halves a
+// side within a factor 2 of the widest, so the subdivision stays exhaustive
+// (the widest side halves at least every K*D splits along a path).
+constexpr double kWideFrac = 0.5;
 
 // Pinned host buffer with a device mirror, bump-allocated per phase: offsets
 // are taken first, then reserve() sizes both sides, then the host side is
@@ -435,6 +440,12 @@ struct Solver {
     c->roff[K] = w;
   }
 
+  double max_width(const Node *m) const {
+    double w = 0.0;
+    for (int q = 0; q < K * D; ++q) w = std::max(w, (double)m->hi[q] - m->lo[q]);
+    return w;
+  }
+
   // Section 4.1.3: mu_1^1 <= ... <= mu_1^K on the first attribute.
   bool apply_symmetry(std::vector<float> &lo, std::vector<float> &hi) const {
     for (int k = 1; k < K; ++k) lo[k * D] = std::max(lo[k * D], lo[(k - 1) * D]);
@@ -718,11 +729,14 @@ struct Solver {
     std::vector<int> row_node, row_q;
     for (int i = 0; i < nn; ++i) {
       const Node *m = nodes[i];
-      for (int q = 0; q < K * D; ++q)
-        if ((double)m->hi[q] - m->lo[q] > 0) {
+      const double wmax = max_width(m);
+      for (int q = 0; q < K * D; ++q) {
+        const double w = (double)m->hi[q] - m->lo[q];
+        if (w > 0 && w >= kWideFrac * wmax) {
           row_node.push_back(i);
           row_q.push_back(q);
         }
+      }
     }
     const int64_t rows = (int64_t)row_node.size();
     if (rows == 0) return KC_OK;
@@ -765,10 +779,11 @@ struct Solver {
     std::vector<Cand> cands;
     for (int i = 0; i < (int)nodes.size(); ++i) {
       const Node *m = nodes[i];
+      const double wmax = max_width(m);
       for (int k = 0; k < K; ++k)
         for (int a = 0; a < D; ++a) {
           const float l = m->lo[k * D + a], hh = m->hi[k * D + a];
-          if (!(l < hh)) continue;
+          if (!(l < hh) || (double)hh - l < kWideFrac * wmax) continue;
           float lh, rl;
           split_interval(l, hh, &lh, &rl);
           std::vector<float> L1 = m->lo, H1 = m->hi, L2 = m->lo, H2 = m->hi;

@@ -1,0 +1,247 @@
+"""Learned branching for the device branch and bound.
+
+The paper splits the widest center box at its midpoint (Section 3.3). Here a
+small network scores every positive-width (cluster, attribute) candidate of a
+node instead, imitating strong branching:
+
+collect   runs kc_solve on seeded training instances with strong-branching
+          recording: at labelled nodes every candidate split is bounded on the
+          device and scored max(dL, e) * max(dR, e) (the product score of
+          strong branching); one feature row per candidate is kept.
+train     fits the 32-64-64-64-1 network with the library's own forward,
+          backward, loss and Adam kernels (bf16 weights, float32 master copy);
+          the target of a node is its best-scoring candidate.
+evaluate  solves the same instances with the max-range rule and with the
+          network and reports time to certified optimum (or the gap at the
+          time cap), nodes and solved counts.
+
+Usage: python -m paper_2301_00061_amd.learn all --instances 400 --out <weights.npz>
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import datagen  # noqa: E402
+
+from . import api  # noqa: E402
+
+WEIGHTS = os.path.join(HERE, "branching_net.npz")
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+# ------------------------------------------------------------------ collect
+
+def collect(seeds, n, max_nodes=512, first=32, every=8, batch=64, cap=200_000):
+    """Strong-branching rows of the given training instances. Returns a dict
+    with feat [R,32] float32, grp_off [G+1] int32 and target [G] int32."""
+    feats, offs, tgts = [], [0], []
+    buf = api.StrongBranchingBuffer(cap, first, every)
+    t0 = time.time()
+    for i, seed in enumerate(seeds):
+        x, k = datagen.learned_instance_device(seed, n)
+        torch.cuda.synchronize()
+        r = api.solve(x, n, k, batch=batch, i_sr=2, max_nodes=max_nodes, sb=buf)
+        m = r["sb_rows"]
+        node = buf.node[:m]
+        score = buf.score[:m]
+        feat = buf.feat[:m]
+        # groups of consecutive rows with the same labelled node
+        starts = np.concatenate([[0], np.nonzero(np.diff(node))[0] + 1, [m]])
+        for a, b in zip(starts[:-1], starts[1:]):
+            if b - a < 2:
+                continue
+            sc = score[a:b]
+            if sc.max() <= sc.min():  # no signal
+                continue
+            feats.append(feat[a:b])
+            offs.append(offs[-1] + (b - a))
+            tgts.append(int(np.argmax(sc)))
+        del x
+        if (i + 1) % 25 == 0:
+            log(f"[collect] {i + 1}/{len(seeds)} instances, {len(tgts)} labelled nodes, "
+                f"{offs[-1]} rows, {time.time() - t0:.1f}s")
+    return dict(feat=np.concatenate(feats).astype(np.float32) if feats else np.zeros((0, 32), np.float32),
+                grp_off=np.array(offs, dtype=np.int32), target=np.array(tgts, dtype=np.int32))
+
+
+# -------------------------------------------------------------------- train
+
+def _to_bf16_device(w32: torch.Tensor, h) -> torch.Tensor:
+    """bf16 copy of the master weights, rounded by the library (an Adam step
+    with zero gradient and zero learning rate leaves w32 unchanged)."""
+    wb = torch.empty(w32.numel(), dtype=torch.int16, device=w32.device)
+    z = torch.zeros_like(w32)
+    api.mlp_adam(w32, wb, z, z.clone(), z.clone(), 1, 0.0, h=h)
+    return wb
+
+
+def _batch(data, groups):
+    off = data["grp_off"]
+    rows = np.concatenate([np.arange(off[g], off[g + 1]) for g in groups])
+    sizes = np.array([off[g + 1] - off[g] for g in groups])
+    goff = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int32)
+    return data["feat"][rows], goff, data["target"][groups].astype(np.int32)
+
+
+def accuracy(wb, data, groups, h=None):
+    if len(groups) == 0:
+        return float("nan")
+    feat, goff, tgt = _batch(data, groups)
+    s, _ = api.mlp_forward(wb, torch.from_numpy(feat).cuda(), h=h)
+    s = s.cpu().numpy()
+    hit = [int(np.argmax(s[goff[i]:goff[i + 1]])) == tgt[i] for i in range(len(groups))]
+    return float(np.mean(hit))
+
+
+def train(data, epochs=30, lr=2e-3, groups_per_step=256, seed=0, val_frac=0.1):
+    h = api.handle()
+    G = len(data["target"])
+    rng = np.random.Generator(np.random.PCG64(seed))
+    perm = rng.permutation(G)
+    n_val = int(G * val_frac)
+    val, tr = perm[:n_val], perm[n_val:]
+    w32 = torch.from_numpy(datagen.mlp_init_weights(seed)).cuda()
+    wb = _to_bf16_device(w32, h)
+    m = torch.zeros_like(w32)
+    v = torch.zeros_like(w32)
+    step = 0
+    hist = []
+    for ep in range(epochs):
+        rng.shuffle(tr)
+        tot, cnt = 0.0, 0
+        for b0 in range(0, len(tr), groups_per_step):
+            grp = tr[b0:b0 + groups_per_step]
+            feat, goff, tgt = _batch(data, grp)
+            fd = torch.from_numpy(feat).cuda()
+            s, act = api.mlp_forward(wb, fd, want_act=True, h=h)
+            loss, ds = api.mlp_loss(s, torch.from_numpy(goff).cuda(), torch.from_numpy(tgt).cuda(), h=h)
+            dw = api.mlp_backward(wb, fd, act, ds, h=h)
+            step += 1
+            api.mlp_adam(w32, wb, dw, m, v, step, lr, h=h)
+            tot += loss.item() * len(grp)
+            cnt += len(grp)
+        acc_tr = accuracy(wb, data, tr[:2000], h)
+        acc_va = accuracy(wb, data, val, h)
+        hist.append(dict(epoch=ep, loss=tot / max(1, cnt), acc_train=acc_tr, acc_val=acc_va))
+        log(f"[train] epoch {ep} loss {tot / max(1, cnt):.4f} top1 train {acc_tr:.3f} val {acc_va:.3f}")
+    # agreement of the max-range rule with strong branching, for reference
+    return w32, wb, hist
+
+
+def max_range_agreement(data, groups):
+    """Top-1 agreement of the max-range rule (widest side; feature 13 is the
+    side's width over the node's widest side) with the strong-branching label."""
+    off = data["grp_off"]
+    hit = []
+    for g in groups:
+        f = data["feat"][off[g]:off[g + 1]]
+        hit.append(int(np.argmax(f[:, 13])) == data["target"][g])
+    return float(np.mean(hit)) if hit else float("nan")
+
+
+def save(path, w32, wb, meta):
+    np.savez(path, w32=w32.cpu().numpy(), w_bf16=wb.cpu().numpy().view(np.uint16),
+             meta=np.frombuffer(json.dumps(meta).encode(), dtype=np.uint8))
+
+
+def load(path=WEIGHTS, device="cuda"):
+    z = np.load(path, allow_pickle=False)
+    wb = torch.from_numpy(z["w_bf16"].view(np.int16).copy()).to(device)
+    meta = json.loads(bytes(z["meta"]).decode()) if "meta" in z else {}
+    return wb, meta
+
+
+# ----------------------------------------------------------------- evaluate
+
+def shifted_geomean(ts, shift=1.0):
+    return math.exp(sum(math.log(t + shift) for t in ts) / len(ts)) - shift
+
+
+def evaluate(seeds, n, k, wb, time_limit, batch=64):
+    rows = []
+    for seed in seeds:
+        x, kk = datagen.learned_instance_device(seed, n, k=k)
+        torch.cuda.synchronize()
+        res = {}
+        for rule in ("plain", "learned"):
+            r = api.solve(x, n, kk, batch=batch, i_sr=2, time_limit_s=time_limit,
+                          branching=1 if rule == "learned" else 0,
+                          mlp_w=wb if rule == "learned" else None)
+            res[rule] = dict(seconds=r["seconds"], nodes=r["nodes"], gap=r["gap"],
+                             solved=r["status"] == 0, obj=r["obj"])
+        rows.append(dict(seed=seed, k=kk, n=n, **res))
+        log(f"[eval] seed {seed} K={kk} plain {res['plain']['seconds']:.2f}s/{res['plain']['nodes']} "
+            f"gap {res['plain']['gap']:.2e} | learned {res['learned']['seconds']:.2f}s/"
+            f"{res['learned']['nodes']} gap {res['learned']['gap']:.2e}")
+        del x
+    summ = {}
+    for rule in ("plain", "learned"):
+        ts = [r[rule]["seconds"] for r in rows]
+        summ[rule] = dict(solved=sum(r[rule]["solved"] for r in rows),
+                          sgm_seconds=shifted_geomean(ts),
+                          sgm_nodes=shifted_geomean([r[rule]["nodes"] for r in rows]),
+                          mean_gap=float(np.mean([r[rule]["gap"] for r in rows])))
+    return rows, summ
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("cmd", choices=["all", "eval"])
+    ap.add_argument("--instances", type=int, default=400)
+    ap.add_argument("--n", type=int, default=1_000_000)
+    ap.add_argument("--max-nodes", type=int, default=512)
+    ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--out", default=WEIGHTS)
+    ap.add_argument("--weights", default=WEIGHTS)
+    ap.add_argument("--eval-seeds", default="10000:10010")
+    ap.add_argument("--eval-n", type=int, default=1_000_000)
+    ap.add_argument("--eval-k", type=int, default=0)
+    ap.add_argument("--time-limit", type=float, default=30.0)
+    ap.add_argument("--report", default=None)
+    a = ap.parse_args(argv)
+    torch.cuda.set_device(0)
+    report = {}
+    if a.cmd == "all":
+        t0 = time.time()
+        data = collect(range(a.instances), a.n, max_nodes=a.max_nodes)
+        log(f"[collect] {len(data['target'])} labelled nodes, {len(data['feat'])} rows, "
+            f"{time.time() - t0:.1f}s")
+        w32, wb, hist = train(data, epochs=a.epochs)
+        G = len(data["target"])
+        meta = dict(instances=a.instances, n=a.n, max_nodes=a.max_nodes,
+                    labelled_nodes=int(G), rows=int(len(data["feat"])), history=hist,
+                    max_range_agreement=max_range_agreement(data, np.arange(G)))
+        save(a.out, w32, wb, meta)
+        log(f"[train] saved {a.out}; max-range agreement with strong branching "
+            f"{meta['max_range_agreement']:.3f}")
+        report["train"] = meta
+    else:
+        wb, meta = load(a.weights)
+    lo, hi = (int(v) for v in a.eval_seeds.split(":"))
+    rows, summ = evaluate(range(lo, hi), a.eval_n, a.eval_k or None, wb, a.time_limit)
+    report["eval"] = dict(rows=rows, summary=summ, n=a.eval_n, k=a.eval_k or "U{4..8}",
+                          time_limit=a.time_limit)
+    log("[eval] summary " + json.dumps(summ))
+    if a.report:
+        with open(a.report, "w") as f:
+            json.dump(report, f, indent=1)
+
+
+if __name__ == "__main__":
+    main()

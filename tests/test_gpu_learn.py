@@ -1,0 +1,48 @@
+"""Learned branching: strong-branching labels from the device branch and bound,
+training with the library's kernels, and certified optimality unchanged when
+the network chooses the splits."""
+import numpy as np
+import pytest
+import torch
+
+import datagen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def kc():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2301_00061_amd import api, learn
+    return api, learn
+
+
+def test_collect_and_train(kc):
+    api, learn = kc
+    data = learn.collect(range(3), 20000, max_nodes=96, first=16, every=4)
+    off, tgt, feat = data["grp_off"], data["target"], data["feat"]
+    assert len(tgt) > 5 and feat.shape == (off[-1], 32)
+    sizes = np.diff(off)
+    assert np.all(sizes >= 2) and np.all((tgt >= 0) & (tgt < sizes))
+    assert np.all(np.isfinite(feat))
+    w32, wb, hist = learn.train(data, epochs=3, groups_per_step=16)
+    assert all(np.isfinite(h["loss"]) for h in hist)
+    assert torch.isfinite(w32).all()
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_learned_branching_keeps_the_optimum(kc, seed):
+    """Any network (here an untrained one) only changes which side is split;
+    the certified optimum stays the oracle's."""
+    api, learn = kc
+    X = datagen.small_mixture(seed)
+    X64 = X.astype(np.float64)
+    opt = oracle.solve(X64, 3)["obj"]
+    w32 = torch.from_numpy(datagen.mlp_init_weights(seed)).cuda()
+    wb = learn._to_bf16_device(w32, api.handle())
+    r = api.solve(api.to_device_soa(X), len(X), 3, batch=16, branching=1, mlp_w=wb)
+    assert r["status"] == 0
+    assert abs(r["obj"] - opt) <= 1e-6 * opt and r["lb"] <= opt * (1 + 1e-12)
+    obj, _ = oracle.objective(X64, X64[r["centers"]][None])
+    assert obj[0] == r["obj"]
