@@ -47,10 +47,15 @@ def log(*a):
 
 # ------------------------------------------------------------------ collect
 
-def collect(seeds, n, max_nodes=512, first=32, every=8, batch=64, cap=200_000):
+def collect(seeds, n, max_nodes=512, first=32, every=8, batch=64, cap=200_000, min_ratio=1.5):
     """Strong-branching rows of the given training instances. Returns a dict
-    with feat [R,32] float32, grp_off [G+1] int32 and target [G] int32."""
+    with feat [R,32] float32, grp_off [G+1] int32 and target [G] int32.
+
+    A labelled node is kept only when its best candidate's score is at least
+    `min_ratio` times the runner-up's (a clear winner); nodes whose candidates
+    all leave the bound unchanged carry no label."""
     feats, offs, tgts = [], [0], []
+    stats = dict(nodes=0, flat=0, weak=0, kept=0)
     buf = api.StrongBranchingBuffer(cap, first, every)
     t0 = time.time()
     for i, seed in enumerate(seeds):
@@ -58,17 +63,25 @@ def collect(seeds, n, max_nodes=512, first=32, every=8, batch=64, cap=200_000):
         torch.cuda.synchronize()
         r = api.solve(x, n, k, batch=batch, i_sr=2, max_nodes=max_nodes, sb=buf)
         m = r["sb_rows"]
-        node = buf.node[:m]
-        score = buf.score[:m]
-        feat = buf.feat[:m]
+        # copies: the buffer is refilled by the next instance
+        node = buf.node[:m].copy()
+        score = buf.score[:m].copy()
+        feat = buf.feat[:m].copy()
         # groups of consecutive rows with the same labelled node
         starts = np.concatenate([[0], np.nonzero(np.diff(node))[0] + 1, [m]])
         for a, b in zip(starts[:-1], starts[1:]):
             if b - a < 2:
                 continue
+            stats["nodes"] += 1
             sc = score[a:b]
             if sc.max() <= sc.min():  # no signal
+                stats["flat"] += 1
                 continue
+            top2 = np.sort(sc)[-2:]
+            if top2[1] < min_ratio * top2[0]:
+                stats["weak"] += 1
+                continue
+            stats["kept"] += 1
             feats.append(feat[a:b])
             offs.append(offs[-1] + (b - a))
             tgts.append(int(np.argmax(sc)))
@@ -76,8 +89,10 @@ def collect(seeds, n, max_nodes=512, first=32, every=8, batch=64, cap=200_000):
         if (i + 1) % 25 == 0:
             log(f"[collect] {i + 1}/{len(seeds)} instances, {len(tgts)} labelled nodes, "
                 f"{offs[-1]} rows, {time.time() - t0:.1f}s")
+    log(f"[collect] label stats {stats}")
     return dict(feat=np.concatenate(feats).astype(np.float32) if feats else np.zeros((0, 32), np.float32),
-                grp_off=np.array(offs, dtype=np.int32), target=np.array(tgts, dtype=np.int32))
+                grp_off=np.array(offs, dtype=np.int32), target=np.array(tgts, dtype=np.int32),
+                stats=stats)
 
 
 # -------------------------------------------------------------------- train
@@ -140,7 +155,6 @@ def train(data, epochs=30, lr=2e-3, groups_per_step=256, seed=0, val_frac=0.1):
         acc_va = accuracy(wb, data, val, h)
         hist.append(dict(epoch=ep, loss=tot / max(1, cnt), acc_train=acc_tr, acc_val=acc_va))
         log(f"[train] epoch {ep} loss {tot / max(1, cnt):.4f} top1 train {acc_tr:.3f} val {acc_va:.3f}")
-    # agreement of the max-range rule with strong branching, for reference
     return w32, wb, hist
 
 
@@ -207,6 +221,7 @@ def main(argv=None):
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--max-nodes", type=int, default=512)
     ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--min-ratio", type=float, default=1.5)
     ap.add_argument("--out", default=WEIGHTS)
     ap.add_argument("--weights", default=WEIGHTS)
     ap.add_argument("--eval-seeds", default="10000:10010")
@@ -219,13 +234,14 @@ def main(argv=None):
     report = {}
     if a.cmd == "all":
         t0 = time.time()
-        data = collect(range(a.instances), a.n, max_nodes=a.max_nodes)
+        data = collect(range(a.instances), a.n, max_nodes=a.max_nodes, min_ratio=a.min_ratio)
         log(f"[collect] {len(data['target'])} labelled nodes, {len(data['feat'])} rows, "
             f"{time.time() - t0:.1f}s")
         w32, wb, hist = train(data, epochs=a.epochs)
         G = len(data["target"])
         meta = dict(instances=a.instances, n=a.n, max_nodes=a.max_nodes,
                     labelled_nodes=int(G), rows=int(len(data["feat"])), history=hist,
+                    label_stats=data["stats"], mean_group=float(len(data["feat"]) / max(1, G)),
                     max_range_agreement=max_range_agreement(data, np.arange(G)))
         save(a.out, w32, wb, meta)
         log(f"[train] saved {a.out}; max-range agreement with strong branching "

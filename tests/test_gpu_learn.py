@@ -31,6 +31,17 @@ def test_collect_and_train(kc):
     assert torch.isfinite(w32).all()
 
 
+def test_collect_rows_belong_to_their_instance(kc):
+    """Rows collected over several instances equal those collected from each
+    instance alone (the recording buffer is reused between instances)."""
+    api, learn = kc
+    both = learn.collect([0, 1], 20000, max_nodes=64, first=8, every=4, min_ratio=1.0)
+    one = [learn.collect([s], 20000, max_nodes=64, first=8, every=4, min_ratio=1.0) for s in (0, 1)]
+    assert np.array_equal(both["feat"], np.concatenate([d["feat"] for d in one]))
+    assert np.array_equal(both["target"], np.concatenate([d["target"] for d in one]))
+    assert len(one[0]["target"]) > 0 and len(one[1]["target"]) > 0
+
+
 @pytest.mark.parametrize("seed", [0, 1, 2])
 def test_learned_branching_keeps_the_optimum(kc, seed):
     """Any network (here an untrained one) only changes which side is split;
