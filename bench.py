@@ -11,9 +11,10 @@ candidates, the float32 objective screen and the float64 certificate of every
 improvement. The search is deterministic, so every step does identical work.
 
 value = sample-box bound evaluations of the step / wall time of the step
-(inputs already resident in HBM). The roofline object describes the batched
-lower-bound kernel, timed with HIP events on the driver's stream; the CPU
-baseline times the float64 oracle's lower bound on a bounded sample.
+(inputs already resident in HBM). The roofline object describes the kernel
+with the largest share of the step (tightening or lower bound), timed with HIP
+events on the driver's stream; the CPU baseline times the float64 oracle's
+lower bound on a bounded sample.
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -33,10 +34,40 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 VALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12  # fp32 VALU lane-ops/s (= 157.3 TFLOP/s with FMA = 2)
 
+# passes=None: a step is one solve to the certified optimum
 WORKLOADS = {
     "mixture_10m_d4_k5": dict(n=10_000_000, d=4, k=5, std=0.1, outliers=0.01, seed=0,
                               batch=64, i_sr=2, passes=40),
+    "mixture_1b_d2_k3": dict(n=1_000_000_000, d=2, k=3, std=0.05, outliers=0.0, seed=0,
+                             batch=64, i_sr=1, passes=None),
 }
+
+
+KERNEL_SOURCES = {
+    "k_tighten": ["kc_tighten.hip", "kc_device.h", "kc_internal.h"],
+    "k_bound": ["kc_bound.hip", "kc_bound_impl.h", "kc_device.h", "kc_internal.h"],
+}
+
+
+def profiled_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary of
+    this workload (FETCH_SIZE + WRITE_SIZE scaled by a plain copy of known
+    size), or None when there is none or the kernel's sources changed since
+    the counters were taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    h = re.search(r"sources_sha256:\s*([0-9a-f]{64})", txt)
+    if not m or not h:
+        return None
+    hs = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel]:
+        hs.update(open(os.path.join(ROOT, "paper_2301_00061_amd", "csrc", f), "rb").read())
+    return float(m.group(1)) if hs.hexdigest() == h.group(1) else None
 
 
 def cpu_baseline(d: int, k: int, nodes: int, budget_s: float = 12.0):
@@ -91,7 +122,11 @@ def main() -> int:
     torch.cuda.synchronize()
     h = api.handle()
     n, k, d = W["n"], W["k"], W["d"]
-    opts = dict(batch=W["batch"], i_sr=W["i_sr"], max_nodes=W["passes"] * W["batch"])
+    opts = dict(batch=W["batch"], i_sr=W["i_sr"], max_nodes=W["passes"] * W["batch"] if W["passes"] else 0)
+
+    # one plain device copy of the points (known size: read and write
+    # d * ld * 4 bytes), untimed: scales the profiler's HBM byte counters
+    torch.empty_like(x).copy_(x)
 
     # autotune the batched lower-bound shape of the driver (untimed set-up)
     off, lo, hi = datagen.random_boxes(2 * W["batch"], k, d, 1, wmin=0.05, wmax=1.0)
@@ -108,8 +143,21 @@ def main() -> int:
     T = (t1 - t0) / args.steps
     evals = sum(r["evals"] for r in runs) / args.steps
     lb_s = sum(r["lb_kernel_ms"] for r in runs) / args.steps / 1e3
-    ops_per_eval = 3 * d + 1  # clamp, subtract, multiply-add per attribute; min over boxes
-    achieved = evals * ops_per_eval / lb_s / 1e12
+    t_evals = sum(r["tighten_evals"] for r in runs) / args.steps
+    t_s = sum(r["tighten_kernel_ms"] for r in runs) / args.steps / 1e3
+    # algorithmic VALU lane-ops per sample-box evaluation: clamp, subtract and
+    # multiply-add per attribute, one compare / min per box
+    ops_per_eval = 3 * d + 1
+    kernels = {
+        "k_tighten": {"evals": t_evals, "seconds": t_s,
+                      "what": "assignment and tightening aggregates (Algorithms 3-4)"},
+        "k_bound": {"evals": evals, "seconds": lb_s,
+                    "what": "batched lower bound with upper-bound candidates (Section 3.1)"},
+    }
+    for v in kernels.values():
+        v["achieved"] = v["evals"] * ops_per_eval / max(v["seconds"], 1e-12) / 1e12
+        v["frac"] = v["achieved"] / VALU_PEAK_TOPS
+    dom = max(kernels, key=lambda k: kernels[k]["seconds"])
     r0 = runs[0]
 
     base = None
@@ -135,10 +183,15 @@ def main() -> int:
                    "batch_nodes": W["batch"], "passes_per_step": W["passes"],
                    "sample_reduction_every": W["i_sr"], "nodes_per_step": r0["nodes"],
                    "gap_after_step": r0["gap"], "incumbent": r0["obj"],
+                   "certified_optimal": r0["status"] == 0, "solve_seconds": r0["seconds"],
                    "lb_kernel_ms_per_step": lb_s * 1e3},
-        "roofline": {"bound": "alu", "kernel": "k_bound (batched lower bound + candidates)",
-                     "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "Tlane-op/s",
-                     "frac": achieved / VALU_PEAK_TOPS, "traffic": None},
+        "roofline": {"bound": "alu", "kernel": dom, "achieved": kernels[dom]["achieved"],
+                     "peak": VALU_PEAK_TOPS, "unit": "Tlane-op/s", "frac": kernels[dom]["frac"],
+                     "traffic": profiled_traffic(dom, args.workload),
+                     "share_of_step": kernels[dom]["seconds"] / T},
+        "kernels": {k: {"achieved_tlane_ops": v["achieved"], "frac": v["frac"],
+                        "ms_per_step": v["seconds"] * 1e3, "evals_per_step": v["evals"]}
+                    for k, v in kernels.items()},
         "cpu_baseline": base,
     }
     print(json.dumps(line))

@@ -250,6 +250,8 @@ typedef struct {
   int64_t n_active;     /* samples left after sample reduction               */
   double seconds;       /* wall time                                         */
   double lb_kernel_ms;  /* total time inside kc_lower_bound launches         */
+  double tighten_kernel_ms; /* total time inside kc_tighten launches        */
+  int64_t tighten_evals;    /* sample-box evaluations of the tightening passes */
   int32_t seeds_found;
   int32_t status;       /* 0 closed (gap <= eps_rel), 1 node limit, 2 time limit */
   int32_t sb_rows;      /* strong-branching rows written                     */

@@ -52,6 +52,7 @@ class Result(C.Structure):
                 ("fft_obj", C.c_double), ("centers", C.c_int64 * 64), ("nodes", C.c_int64),
                 ("passes", C.c_int64), ("evals", C.c_int64), ("n_active", C.c_int64),
                 ("seconds", C.c_double), ("lb_kernel_ms", C.c_double),
+                ("tighten_kernel_ms", C.c_double), ("tighten_evals", C.c_int64),
                 ("seeds_found", C.c_int32), ("status", C.c_int32), ("sb_rows", C.c_int32),
                 ("sb_nodes", C.c_int32)]
 

@@ -245,6 +245,7 @@ def solve(x, n, k, batch=64, i_sr=4, use_bt=True, use_seeds=True, max_refs=50, b
     return dict(obj=r.obj, lb=r.lb, gap=r.gap, fft_obj=r.fft_obj,
                 centers=np.array(r.centers[:k]), nodes=r.nodes, passes=r.passes, evals=r.evals,
                 n_active=r.n_active, seconds=r.seconds, lb_kernel_ms=r.lb_kernel_ms,
+                tighten_kernel_ms=r.tighten_kernel_ms, tighten_evals=r.tighten_evals,
                 seeds_found=bool(r.seeds_found), status=r.status, sb_rows=r.sb_rows,
                 sb_nodes=r.sb_nodes)
 

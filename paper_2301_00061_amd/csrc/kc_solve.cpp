@@ -195,6 +195,7 @@ struct Solver {
   double t0 = 0;
   // wall time per phase (reported with verbose)
   double t_tighten = 0, t_reduce = 0, t_branch = 0, t_bound = 0;
+  double last_pass_s = 0;  // wall time of the previous pass without its reduction
   int64_t sr_interval = 0, sr_runs = 0;
 
   Solver(kc_handle *h_, const kc_points *x, const kc_opts *op, kc_result *r)
@@ -486,12 +487,15 @@ struct Solver {
     if ((s = upload())) return s;
     const kc_nodes nd = dev_nodes(P);
     const kc_refs rf = dev_refs(P);
+    (void)hipEventRecord(h->ev0, st);
     s = kc_tighten(h, &act, &nd, a_bt, P.refs ? &rf : nullptr, out.dp<float>(o_bl), out.dp<float>(o_bh),
                    out.dp<uint32_t>(o_ni), out.dp<float>(o_am), out.dp<float>(o_ax),
                    out.dp<uint32_t>(o_na), out.dp<uint32_t>(o_ne),
                    want_far ? out.dp<int64_t>(o_far) : nullptr, nullptr, st);
+    (void)hipEventRecord(h->ev1, st);
     if (s) return s;
     res->passes++;
+    res->tighten_evals += act.n * (int64_t)nn * K;
     // coordinates and original ids of the new refs, gathered before any
     // sample reduction moves the active samples
     if (want_far &&
@@ -499,6 +503,11 @@ struct Solver {
                        out.dp<int64_t>(o_fo), st)))
       return s;
     if ((s = download("tighten"))) return s;
+    {
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, h->ev0, h->ev1);
+      res->tighten_kernel_ms += ms;
+    }
 
     const float *bbl = out.hp<float>(o_bl), *bbh = out.hp<float>(o_bh);
     const float *amn = out.hp<float>(o_am), *amx = out.hp<float>(o_ax);
@@ -883,6 +892,8 @@ struct Solver {
       // bounds tightening
       const double a_bt = o.use_bt ? alpha_ub : INFINITY;
       double tp = now_s();
+      const double pass_start = tp;
+      double sr_cost = 0;
       if ((s = tighten(batch, alive, a_bt))) return s;
       t_tighten += now_s() - tp;
       std::vector<Node *> live;
@@ -897,8 +908,9 @@ struct Solver {
         }
       }
       // sample reduction every i_sr passes, over the open nodes and this
-      // batch; the interval doubles (up to 64 i_sr) while reductions delete
-      // under 1% of the active samples and resets when one deletes more
+      // batch. A reduction that deletes under 1% of the active samples and
+      // costs more than a tenth of a pass doubles the interval (up to
+      // 64 i_sr); any other resets it to i_sr.
       ++passes_since_sr;
       if (o.i_sr > 0 && sr_interval == 0) sr_interval = o.i_sr;
       if (o.i_sr > 0 && passes_since_sr >= sr_interval) {
@@ -907,11 +919,13 @@ struct Solver {
         const int64_t before = act.n;
         if ((s = reduce(live))) return s;
         ++sr_runs;
-        if ((double)(before - act.n) < 0.01 * (double)before)
+        const double cost = now_s() - tp;
+        if ((double)(before - act.n) < 0.01 * (double)before && cost > 0.1 * last_pass_s)
           sr_interval = std::min<int64_t>(sr_interval * 2, (int64_t)o.i_sr * 64);
         else
           sr_interval = o.i_sr;
-        t_reduce += now_s() - tp;
+        t_reduce += cost;
+        sr_cost = cost;
       }
       tp = now_s();
 
@@ -991,6 +1005,7 @@ struct Solver {
       if (!ev.empty())
         if ((s = bound(ev, is_leaf))) return s;
       t_bound += now_s() - tp;
+      last_pass_s = now_s() - pass_start - sr_cost;
 
       if (!heap.empty()) {
         const double lb = global_lb();
