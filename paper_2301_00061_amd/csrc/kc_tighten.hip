@@ -134,7 +134,8 @@ __global__ __launch_bounds__(WG) void k_tighten(TightenArgs A) {
     }
   }
   uint32_t nex = 0;
-  const bool allref = s_allref != 0;
+  const int cnt_u = __builtin_amdgcn_readfirstlane(cnt);
+  const bool allref = __builtin_amdgcn_readfirstlane(s_allref) != 0;
   const bool write_labels = A.labels != nullptr && chunk == 0;
 
   const int64_t s_lo = (int64_t)split * A.span;
@@ -165,81 +166,106 @@ __global__ __launch_bounds__(WG) void k_tighten(TightenArgs A) {
         for (int i = 0; i < S; ++i) xs[i][a] = 0.f;
       }
     }
+    // Center-based assignment (Lemma 1), box-major: each box's bounds are
+    // read from LDS once for the lane's S samples. In the single-chunk case
+    // the same distances record which boxes hold each sample.
+    int n_out[S], keep[S], label[S];
+    uint32_t inm[S];
 #pragma unroll
     for (int i = 0; i < S; ++i) {
-      if (base + i >= s_hi) break;
-      const float *xv = xs[i];
-      const uint32_t sid = (uint32_t)(base + i);
-
-      // Center-based assignment (Lemma 1); in the single-chunk case the same
-      // pass records which boxes hold the sample.
-      int n_out = 0, keep = -1;
-      uint32_t inmask = 0;
-      if (single) {
+      n_out[i] = 0;
+      keep[i] = -1;
+      inm[i] = 0;
+    }
+    if (single) {
 #pragma unroll
-        for (int k = 0; k < KC; ++k) {
-          if (k < cnt) {
+      for (int k = 0; k < KC; ++k) {
+        if (k < cnt_u) {
+          float lo[DM], hi[DM];
+#pragma unroll
+          for (int a = 0; a < DM; ++a) {
+            lo[a] = bx[k * 2 * DM + 2 * a];
+            hi[a] = bx[k * 2 * DM + 2 * a + 1];
+          }
+#pragma unroll
+          for (int i = 0; i < S; ++i) {
             float acc = 0.f;
             bool in = true;
 #pragma unroll
             for (int a = 0; a < DM; ++a) {
               if (a < dd) {
-                const float c = kcd::med3(bx[k * 2 * DM + 2 * a], xv[a], bx[k * 2 * DM + 2 * a + 1]);
-                in = in && (c == xv[a]);
-                const float t = xv[a] - c;
+                const float c = kcd::med3(lo[a], xs[i][a], hi[a]);
+                in = in && (c == xs[i][a]);
+                const float t = xs[i][a] - c;
                 acc = (a == 0) ? t * t : __builtin_fmaf(t, t, acc);
               }
             }
-            if (acc > A.t_center)
-              ++n_out;
-            else
-              keep = k;
-            inmask |= (uint32_t)in << k;
+            const bool out = acc > A.t_center;
+            n_out[i] += out;
+            keep[i] = out ? keep[i] : k;
+            inm[i] |= (uint32_t)in << k;
           }
         }
-      } else {
-        for (int k = 0; k < cnt; ++k) {
+      }
+    } else {
+      for (int k = 0; k < cnt_u; ++k) {
+        float lo[DM], hi[DM];
+#pragma unroll
+        for (int a = 0; a < DM; ++a) {
+          lo[a] = bx[k * 2 * DM + 2 * a];
+          hi[a] = bx[k * 2 * DM + 2 * a + 1];
+        }
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
           float acc = 0.f;
 #pragma unroll
           for (int a = 0; a < DM; ++a) {
             if (a < dd) {
-              const float c = kcd::med3(bx[k * 2 * DM + 2 * a], xv[a], bx[k * 2 * DM + 2 * a + 1]);
-              const float t = xv[a] - c;
+              const float t = xs[i][a] - kcd::med3(lo[a], xs[i][a], hi[a]);
               acc = (a == 0) ? t * t : __builtin_fmaf(t, t, acc);
             }
           }
-          if (acc > A.t_center)
-            ++n_out;
-          else
-            keep = k;
+          const bool out = acc > A.t_center;
+          n_out[i] += out;
+          keep[i] = out ? keep[i] : k;
         }
+      }
 #pragma unroll
-        for (int kk = 0; kk < KC; ++kk) {
-          const int k = c0 + kk;
-          if (k < cnt) {
+      for (int kk = 0; kk < KC; ++kk) {
+        const int k = c0 + kk;
+        if (k < cnt_u) {
+#pragma unroll
+          for (int i = 0; i < S; ++i) {
             bool in = true;
 #pragma unroll
             for (int a = 0; a < DM; ++a)
-              if (a < dd) in = in && (bx[k * 2 * DM + 2 * a] <= xv[a]) && (xv[a] <= bx[k * 2 * DM + 2 * a + 1]);
-            inmask |= (uint32_t)in << kk;
+              if (a < dd)
+                in = in && (bx[k * 2 * DM + 2 * a] <= xs[i][a]) && (xs[i][a] <= bx[k * 2 * DM + 2 * a + 1]);
+            inm[i] |= (uint32_t)in << kk;
           }
         }
       }
-      int label = -1;
-      if (n_out == cnt)
-        label = -2;
-      else if (n_out == cnt - 1)
-        label = keep;
+    }
 
-      // Sample-based assignment (Lemma 2), only for unassigned samples.
-      if (label == -1 && allref) {
-        // cluster k is excluded once one of its refs is farther than 4 alpha;
-        // the scan stops when two clusters remain possible
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+      const float *xv = xs[i];
+      int lab = n_out[i] == cnt_u ? -2 : (n_out[i] == cnt_u - 1 ? keep[i] : -1);
+      if (base + i >= s_hi) {  // past the end: no contribution
+        lab = -3;
+        inm[i] = 0;
+      }
+      // Sample-based assignment (Lemma 2), only for unassigned samples:
+      // cluster k is excluded once one of its refs is farther than 4 alpha;
+      // the scan stops when two clusters remain possible.
+      if (lab == -1 && allref) {
         int n_near = 0, rest_k = -1;
-        for (int k = 0; k < cnt && n_near < 2; ++k) {
+        for (int k = 0; k < cnt_u && n_near < 2; ++k) {
+          const int rb = __builtin_amdgcn_readfirstlane(s_rbeg[k]);
+          const int rc = __builtin_amdgcn_readfirstlane(s_rcnt[k]);
           bool fr = false;
-          for (int r = 0; r < s_rcnt[k]; ++r)
-            if (sqdist(xv, rf + (s_rbeg[k] + r) * DM, dd, DM) > A.t_sample) {
+          for (int r = 0; r < rc; ++r)
+            if (sqdist(xv, rf + (rb + r) * DM, dd, DM) > A.t_sample) {
               fr = true;
               break;
             }
@@ -248,33 +274,44 @@ __global__ __launch_bounds__(WG) void k_tighten(TightenArgs A) {
             rest_k = k;
           }
         }
-        if (n_near == 1) label = rest_k;
+        if (n_near == 1) lab = rest_k;
       }
-      if (write_labels) A.labels[sid] = (int8_t)label;
-      nex += (label == -2);
+      if (write_labels && base + i < s_hi) A.labels[base + i] = (int8_t)lab;
+      nex += (lab == -2);
+      label[i] = lab;
+    }
 
+    // Running aggregates of the chunk's boxes, box-major.
 #pragma unroll
-      for (int kk = 0; kk < KC; ++kk) {
-        const int k = c0 + kk;
-        if (k < cnt) {
-          if (label == k) {
+    for (int kk = 0; kk < KC; ++kk) {
+      const int k = c0 + kk;
+      if (k < cnt_u) {
+        float mid[DM];
+#pragma unroll
+        for (int a = 0; a < DM; ++a) mid[a] = 0.5f * (bx[k * 2 * DM + 2 * a] + bx[k * 2 * DM + 2 * a + 1]);
+        const int rb = __builtin_amdgcn_readfirstlane(s_rbeg[k]);
+        const int rc = __builtin_amdgcn_readfirstlane(s_rcnt[k]);
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+          const float *xv = xs[i];
+          if (label[i] == k) {
             ++nasg[kk];
             float dm = 0.f;
 #pragma unroll
             for (int a = 0; a < DM; ++a) {
               amin[kk][a] = fminf(amin[kk][a], xv[a]);
               amax[kk][a] = fmaxf(amax[kk][a], xv[a]);
-              const float w = xv[a] - 0.5f * (bx[k * 2 * DM + 2 * a] + bx[k * 2 * DM + 2 * a + 1]);
+              const float w = xv[a] - mid[a];
               dm = (a == 0) ? w * w : __builtin_fmaf(w, w, dm);
             }
-            const uint64_t key = kcd::key_max(dm, sid);
+            const uint64_t key = kcd::key_max(dm, (uint32_t)(base + i));
             far[kk] = key > far[kk] ? key : far[kk];
           }
           // S_+^k: inside box k and within the ball of every ref of box k.
-          bool in = (inmask >> (single ? k : kk)) & 1u;
+          bool in = (inm[i] >> (single ? k : kk)) & 1u;
           if (in)
-            for (int r = 0; r < s_rcnt[k]; ++r)
-              if (!(sqdist(xv, rf + (s_rbeg[k] + r) * DM, dd, DM) <= A.t_ball)) {
+            for (int r = 0; r < rc; ++r)
+              if (!(sqdist(xv, rf + (rb + r) * DM, dd, DM) <= A.t_ball)) {
                 in = false;
                 break;
               }

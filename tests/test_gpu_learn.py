@@ -57,3 +57,21 @@ def test_learned_branching_keeps_the_optimum(kc, seed):
     assert abs(r["obj"] - opt) <= 1e-6 * opt and r["lb"] <= opt * (1 + 1e-12)
     obj, _ = oracle.objective(X64, X64[r["centers"]][None])
     assert obj[0] == r["obj"]
+
+
+@pytest.mark.parametrize("seed", [10001, 10005])
+def test_trained_network_needs_fewer_nodes(kc, seed):
+    """The committed trained network (trained on instances 0..599) against the
+    max-range rule on held-out instances (N = 10^6, D = 5, K = 4): the same
+    certified optimum with fewer nodes, and no more wall time."""
+    api, learn = kc
+    wb, meta = learn.load()
+    assert meta["labelled_nodes"] > 1000
+    x, k = datagen.learned_instance_device(seed, 1_000_000, k=4)
+    torch.cuda.synchronize()
+    plain = api.solve(x, 1_000_000, k, batch=64, i_sr=2, time_limit_s=60)
+    learned = api.solve(x, 1_000_000, k, batch=64, i_sr=2, time_limit_s=60, branching=1, mlp_w=wb)
+    assert plain["status"] == 0 and learned["status"] == 0
+    assert abs(learned["obj"] - plain["obj"]) <= 1e-6 * plain["obj"]
+    assert learned["nodes"] < plain["nodes"]
+    assert learned["seconds"] <= plain["seconds"] * 1.1
