@@ -61,7 +61,11 @@ typedef enum {
   KC_EUNSUPPORTED = -4  /* valid request the library does not implement       */
 } kc_status;
 
-/* Samples in device memory (structure of arrays). */
+/* Samples in device memory (structure of arrays). Values are finite float32
+ * numbers; results for NaN or infinite samples are unspecified. The kernels'
+ * results do not depend on the order of the samples (argmax ties go to the
+ * lowest position), but they run faster when consecutive samples are close:
+ * a wavefront whose samples span a small box settles its box tests at once. */
 typedef struct {
   const float *x;  /* [d][ld] */
   int64_t n;       /* number of samples                          */
@@ -78,7 +82,7 @@ typedef struct {
   int32_t reserved;
   const int32_t *box_off;  /* [n_nodes+1], device                          */
   const float *lo;         /* [n_boxes][d], device                         */
-  const float *hi;         /* [n_boxes][d], device                         */
+  const float *hi;         /* [n_boxes][d], device; lo <= hi per attribute  */
 } kc_nodes;
 
 /* Samples known to belong to the cluster of each box (Section 4.1.1: initial
@@ -217,7 +221,10 @@ typedef struct {
                            farthest from its box midpoint per cluster and
                            node); 0 = seeds only                            */
   int32_t branching;    /* 0: max-range rule; 1: learned (needs mlp_w)      */
-  int32_t reserved0;
+  int32_t keep_order;   /* 0: after the root pass the active samples are put in
+                           Morton order over the root box when n >= 65536 (the
+                           certified results do not depend on the order);
+                           1: keep the input order                          */
   int64_t fft_start;    /* first FFT sample                                 */
   int64_t max_nodes;    /* 0 = unlimited                                    */
   double eps_rel;       /* relative gap at which to stop (>= 1e-6 advised)  */

@@ -41,7 +41,7 @@ class Refs(C.Structure):
 class Opts(C.Structure):
     _fields_ = [("k", C.c_int32), ("batch", C.c_int32), ("i_sr", C.c_int32),
                 ("use_bt", C.c_int32), ("use_seeds", C.c_int32), ("max_refs", C.c_int32),
-                ("branching", C.c_int32), ("reserved0", C.c_int32), ("fft_start", C.c_int64), ("max_nodes", C.c_int64), ("eps_rel", C.c_double),
+                ("branching", C.c_int32), ("keep_order", C.c_int32), ("fft_start", C.c_int64), ("max_nodes", C.c_int64), ("eps_rel", C.c_double),
                 ("time_limit_s", C.c_double), ("mlp_w", C.c_void_p), ("verbose", C.c_int32),
                 ("sb_first", C.c_int32), ("sb_every", C.c_int32), ("sb_cap", C.c_int32),
                 ("sb_feat", C.c_void_p), ("sb_score", C.c_void_p), ("sb_node", C.c_void_p)]

@@ -225,14 +225,15 @@ def mlp_adam(w32, w_bf16, dw, m, v, step, lr, h: Handle | None = None):
 
 def solve(x, n, k, batch=64, i_sr=4, use_bt=True, use_seeds=True, max_refs=50, branching=0,
           fft_start=0, max_nodes=0, eps_rel=1e-6, time_limit_s=0.0, mlp_w=None, verbose=False,
-          sb=None, h: Handle | None = None) -> dict:
+          sb=None, keep_order=False, h: Handle | None = None) -> dict:
     """Algorithm 1 on device-resident samples (synchronous)."""
     h = h or handle()
     P = points(x, n)
     o = Opts(k=k, batch=batch, i_sr=i_sr, use_bt=int(use_bt), use_seeds=int(use_seeds),
              max_refs=int(max_refs), branching=int(branching), fft_start=int(fft_start),
              max_nodes=int(max_nodes), eps_rel=float(eps_rel), time_limit_s=float(time_limit_s),
-             mlp_w=mlp_w.data_ptr() if mlp_w is not None else None, verbose=int(verbose))
+             mlp_w=mlp_w.data_ptr() if mlp_w is not None else None, verbose=int(verbose),
+             keep_order=int(bool(keep_order)))
     if sb is not None:
         # strong-branching label recording into host arrays (see StrongBranchingBuffer)
         o.sb_first, o.sb_every, o.sb_cap = sb.first, sb.every, sb.cap

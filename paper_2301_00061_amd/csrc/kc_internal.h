@@ -73,6 +73,14 @@ void kc_tune_save(kc_handle *h);
 kc_status kc_gather(kc_handle *h, const kc_points *p, const int64_t *ids, int count,
                     const uint32_t *idx_map, float *out, int64_t *orig, hipStream_t st);
 
+// Reorders the samples along a Morton curve over the box [lo, hi] (kc_order.hip):
+// x_out / ids_out (leading dimension ld_out) receive the samples of `in` in the
+// new order and their original ids (ids_in maps `in` to original ids, null:
+// identity). Synchronous on `st`.
+kc_status kc_spatial_order(kc_handle *h, const kc_points *in, const uint32_t *ids_in,
+                           const float *lo, const float *hi, float *x_out, uint32_t *ids_out,
+                           int64_t ld_out, hipStream_t st);
+
 #define KC_RETURN_IF(cond, h, st, ...)          \
   do {                                          \
     if (cond) return kc_fail(h, st, __VA_ARGS__); \

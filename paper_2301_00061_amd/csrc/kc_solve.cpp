@@ -620,6 +620,22 @@ struct Solver {
     return KC_OK;
   }
 
+  // Morton order of the active samples over the root box (the kernels'
+  // results do not depend on the order; coherent wavefronts make them faster).
+  kc_status spatial_order() {
+    const int nxt = cur == 0 ? 1 : 0;
+    if (!xbuf[nxt].ensure((size_t)D * X0->ld * 4) || !ibuf[nxt].ensure((size_t)X0->ld * 4))
+      return kc_fail(h, KC_ENOMEM, "sample buffers");
+    kc_status s = kc_spatial_order(h, &act, idx, root_lo.data(), root_hi.data(), xbuf[nxt].as<float>(),
+                                   ibuf[nxt].as<uint32_t>(), X0->ld, st);
+    if (s) return s;
+    cur = nxt;
+    act.x = xbuf[cur].as<float>();
+    act.ld = X0->ld;
+    idx = ibuf[cur].as<uint32_t>();
+    return KC_OK;
+  }
+
   // ------------------------------------------------------------ features --
   // 32 features of candidate (k,a) of node m (tightened boxes), see the
   // branching network's documentation.
@@ -861,6 +877,7 @@ struct Solver {
     if (hipStreamCreate(&st) != hipSuccess) return kc_fail(h, KC_EDEVICE, "stream");
     kc_status s = root();
     if (s) return s;
+    if (!o.keep_order && act.n >= (1 << 16) && (s = spatial_order())) return s;
     int64_t passes_since_sr = 0;
     res->status = 0;
     std::vector<Node *> batch;

@@ -49,12 +49,19 @@ LB_CASES = [
     (777, 2, 3, 40, True, 8),
     (70000, 3, 256, 10, False, 9),
 ]
+# Morton-ordered samples (the wavefront bounding-box skips take over)
+LB_ORDERED = [(60000, 2, 9, 3, False, 10), (50021, 3, 17, 5, True, 11),
+              (40000, 4, 33, 5, False, 12), (30000, 5, 8, 8, True, 13),
+              (70000, 3, 256, 10, False, 14)]
 
 
-@pytest.mark.parametrize("n,d,nn,k,ragged,seed", LB_CASES)
+@pytest.mark.parametrize("n,d,nn,k,ragged,seed,ordered",
+                         [c + (False,) for c in LB_CASES] + [c + (True,) for c in LB_ORDERED])
 @pytest.mark.parametrize("want_cand", [False, True])
-def test_lower_bound_parity(kc, n, d, nn, k, ragged, seed, want_cand):
+def test_lower_bound_parity(kc, n, d, nn, k, ragged, seed, ordered, want_cand):
     X = datagen.gaussian_mixture(n, d, 3, 0.1, seed)
+    if ordered:
+        X = np.ascontiguousarray(X[_morton(X)])
     off, lo, hi = datagen.random_boxes(nn, k, d, seed, wmin=0.01, wmax=0.8, ragged=ragged)
     X64, lo64, hi64 = X.astype(np.float64), lo.astype(np.float64), hi.astype(np.float64)
     lb, am = oracle.lower_bound(X64, off, lo64, hi64)
@@ -126,10 +133,14 @@ def test_lower_bound_is_deterministic(kc):
         assert torch.equal(a, b)
 
 
-@pytest.mark.parametrize("n,d,ns,k,seed", [(1, 2, 1, 1, 0), (4097, 2, 3, 3, 1), (30011, 4, 9, 5, 2),
-                                           (10000, 5, 40, 8, 3), (2000, 11, 2, 4, 4)])
-def test_objective_parity(kc, n, d, ns, k, seed):
+@pytest.mark.parametrize("n,d,ns,k,seed,ordered", [
+    (1, 2, 1, 1, 0, False), (4097, 2, 3, 3, 1, False), (30011, 4, 9, 5, 2, False),
+    (10000, 5, 40, 8, 3, False), (2000, 11, 2, 4, 4, False),
+    (60000, 2, 5, 3, 5, True), (40000, 4, 9, 5, 6, True)])
+def test_objective_parity(kc, n, d, ns, k, seed, ordered):
     X = datagen.gaussian_mixture(n, d, 3, 0.1, seed)
+    if ordered:
+        X = np.ascontiguousarray(X[_morton(X)])
     rng = np.random.default_rng(seed)
     C = np.concatenate([X[rng.integers(0, n, (ns // 2 + 1) * k)].reshape(-1, k, d),
                         datagen.random_centers(ns, k, d, seed)])[:ns]
@@ -153,8 +164,21 @@ def test_objective_parity(kc, n, d, ns, k, seed):
         assert a32[c] in near
 
 
-def _tighten_case(seed, n, d, k, nn=1, with_refs=True, alpha_scale=1.2):
+def _morton(X, bits=10):
+    """Host Morton order of the rows of X (test input preparation only)."""
+    lo, hi = X.min(0), X.max(0)
+    q = np.clip(((X - lo) / np.maximum(hi - lo, 1e-30) * (2 ** bits - 1)).astype(np.int64), 0, 2 ** bits - 1)
+    key = np.zeros(len(X), dtype=np.int64)
+    for b in range(bits):
+        for a in range(X.shape[1]):
+            key |= ((q[:, a] >> b) & 1) << (b * X.shape[1] + a)
+    return np.argsort(key, kind="stable")
+
+
+def _tighten_case(seed, n, d, k, nn=1, with_refs=True, alpha_scale=1.2, ordered=False):
     X = datagen.gaussian_mixture(n, d, k, 0.08, seed)
+    if ordered:  # consecutive samples close together: whole wavefronts decide at once
+        X = np.ascontiguousarray(X[_morton(X)])
     X64 = X.astype(np.float64)
     T = oracle.fft(X64, k, seed % n)
     z, _ = oracle.objective(X64, X64[T][None])
@@ -177,12 +201,17 @@ def _tighten_case(seed, n, d, k, nn=1, with_refs=True, alpha_scale=1.2):
     return X, off, lo, hi, alpha, ref_off, ref
 
 
-@pytest.mark.parametrize("seed,n,d,k,nn,with_refs", [
-    (0, 3000, 2, 3, 1, True), (1, 20000, 2, 3, 1, False), (2, 9001, 3, 5, 1, True),
-    (3, 5000, 4, 5, 6, True), (4, 4000, 5, 8, 3, False), (5, 2500, 2, 10, 4, True),
-    (6, 3000, 10, 3, 2, True), (7, 1, 2, 2, 1, True)])
-def test_tighten_parity(kc, seed, n, d, k, nn, with_refs):
-    X, off, lo, hi, alpha, ref_off, ref = _tighten_case(seed, n, d, k, nn, with_refs)
+@pytest.mark.parametrize("seed,n,d,k,nn,with_refs,ordered,ascale", [
+    (0, 3000, 2, 3, 1, True, False, 1.2), (1, 20000, 2, 3, 1, False, False, 1.2),
+    (2, 9001, 3, 5, 1, True, False, 1.2), (3, 5000, 4, 5, 6, True, False, 1.2),
+    (4, 4000, 5, 8, 3, False, False, 1.2), (5, 2500, 2, 10, 4, True, False, 1.2),
+    (6, 3000, 10, 3, 2, True, False, 1.2), (7, 1, 2, 2, 1, True, False, 1.2),
+    # Morton-ordered samples: the wavefront bounding-box decisions take over
+    (10, 40000, 2, 3, 1, True, True, 1.2), (11, 30001, 3, 5, 4, True, True, 0.6),
+    (12, 20000, 4, 5, 6, False, True, 1.2), (13, 7777, 2, 3, 2, True, True, 0.3),
+    (14, 50000, 5, 4, 3, True, True, 2.0)])
+def test_tighten_parity(kc, seed, n, d, k, nn, with_refs, ordered, ascale):
+    X, off, lo, hi, alpha, ref_off, ref = _tighten_case(seed, n, d, k, nn, with_refs, ascale, ordered)
     X64 = X.astype(np.float64)
     g, eta = _g(kc, d)
     delta = 3 * g + 1e-12

@@ -129,3 +129,19 @@ def test_solve_rejects_bad_arguments(kc):
         kc.solve(xd, len(X), 3, fft_start=len(X))
     with pytest.raises(kc.KCError):
         kc.solve(xd, len(X), 3, batch=0)
+
+
+def test_spatial_order_keeps_the_certified_optimum():
+    """Above 65,536 samples the driver reorders the active samples along a
+    Morton curve; the certified optimum is that of the input order."""
+    from paper_2301_00061_amd import api
+    X = datagen.gaussian_mixture(200_000, 2, 3, 0.05, 21)
+    X64 = X.astype(np.float64)
+    xd = api.to_device_soa(X)
+    a = api.solve(xd, len(X), 3, batch=64, i_sr=2)
+    b = api.solve(xd, len(X), 3, batch=64, i_sr=2, keep_order=True)
+    assert a["status"] == 0 and b["status"] == 0
+    assert abs(a["obj"] - b["obj"]) <= 1e-6 * b["obj"]
+    for r in (a, b):
+        obj, _ = oracle.objective(X64, X64[r["centers"]][None])
+        assert obj[0] == r["obj"] and r["lb"] <= r["obj"]
