@@ -40,6 +40,10 @@ WORKLOADS = {
                               batch=64, i_sr=2, passes=40),
     "mixture_1b_d2_k3": dict(n=1_000_000_000, d=2, k=3, std=0.05, outliers=0.0, seed=0,
                              batch=64, i_sr=1, passes=None),
+    # a step is one lower-bound pass of one node (K boxes) over all samples:
+    # the per-node bound evaluation itself, bound by HBM bandwidth
+    "lb_1b_d2_k3": dict(n=1_000_000_000, d=2, k=3, std=0.05, outliers=0.0, seed=0,
+                        lb_pass=True),
 }
 
 
@@ -96,6 +100,57 @@ def cpu_baseline(d: int, k: int, nodes: int, budget_s: float = 12.0):
     return evals / spent, f"oracle lower bound, {nodes} nodes x {k} boxes, up to {n} samples, {spent:.1f} s"
 
 
+def lb_pass(args, W) -> int:
+    """One node of K boxes (side 0.1 around the mixture means) bounded over all
+    samples per step; HIP events on the launch stream time the kernel."""
+    import numpy as np
+    import torch
+
+    import datagen
+    from paper_2301_00061_amd import api
+
+    n, d, k = W["n"], W["d"], W["k"]
+    x = datagen.gaussian_mixture_device(n, d, k, W["std"], W["seed"], outlier_frac=W["outliers"])
+    means = datagen._means(W["seed"], k, d).astype(np.float32)
+    off = torch.tensor([0, k], dtype=torch.int32, device="cuda")
+    lo = torch.from_numpy(means - 0.05).cuda()
+    hi = torch.from_numpy(means + 0.05).cuda()
+    torch.empty_like(x).copy_(x)  # plain copy of known size (counter calibration)
+    api.autotune(x, n, off, lo, hi, with_cand=False, k_max=k)
+    for _ in range(args.warmup):
+        api.lower_bound(x, n, off, lo, hi, k_max=k)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(args.steps):
+        lb_raw, _, am, _ = api.lower_bound(x, n, off, lo, hi, k_max=k)
+    e1.record()
+    torch.cuda.synchronize()
+    T = (time.perf_counter() - t0) / args.steps
+    ker = e0.elapsed_time(e1) / 1e3 / args.steps
+    gbs = n * d * 4 / ker / 1e9  # algorithmic bytes: every sample read once
+    base = None
+    if not args.no_cpu_baseline:
+        v, sample = cpu_baseline(d, k, 1)
+        base = {"value": v, "unit": "sample-box evals/s", "cores": 1, "kind": "oracle",
+                "sample": sample}
+    line = {
+        "metric": "sample-box bound evals/s (% HBM peak); time to certified optimum, learned vs plain",
+        "value": n * k / T, "unit": "sample-box evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": T * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "d": d, "k": k, "nodes": 1,
+                   "lb": float(lb_raw[0]), "argmax": int(am[0]), "kernel_ms_per_step": ker * 1e3},
+        "roofline": {"bound": "hbm", "kernel": "k_bound", "achieved": gbs, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                     "traffic": profiled_traffic("k_bound", args.workload)},
+        "cpu_baseline": base,
+    }
+    print(json.dumps(line))
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,6 +172,8 @@ def main() -> int:
 
     W = WORKLOADS[args.workload]
     torch.cuda.set_device(0)
+    if W.get("lb_pass"):
+        return lb_pass(args, W)
     x = datagen.gaussian_mixture_device(W["n"], W["d"], W["k"], W["std"], W["seed"],
                                         outlier_frac=W["outliers"])
     torch.cuda.synchronize()

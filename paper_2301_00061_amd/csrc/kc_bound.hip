@@ -56,21 +56,27 @@ static kc_status dispatch64(int d, const Obj64Args &A, int splits, size_t lds, h
 
 // Reduces the per-split partial keys. mode 0: lower bound (rounded down),
 // mode 1: float32 objective (rounded up).
-__global__ void k_bound_finalize(const uint64_t *part_key, int n_nodes, int splits,
-                                 const uint64_t *part_cand, int n_boxes, int mode, double rel,
-                                 double abs_, float *val_raw, double *val_bound, int64_t *argmax,
-                                 int64_t *cand) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n_nodes) {
+// One wavefront per node (blocks [0, n_nodes)) and, with candidates, one per
+// box (blocks [n_nodes, n_nodes + n_boxes)): lanes stride over the splits'
+// partial keys, a shuffle reduction combines them. Max / min of packed keys
+// does not depend on the order, so the result is the serial reduction's.
+__global__ __launch_bounds__(64) void k_bound_finalize(
+    const uint64_t *part_key, int n_nodes, int splits, const uint64_t *part_cand, int n_boxes,
+    int mode, double rel, double abs_, float *val_raw, double *val_bound, int64_t *argmax,
+    int64_t *cand) {
+  const int b = blockIdx.x, lane = threadIdx.x;
+  if (b < n_nodes) {
     uint64_t key = 0;
-    for (int sp = 0; sp < splits; ++sp) {
-      const uint64_t v = part_key[(int64_t)sp * n_nodes + i];
+    for (int sp = lane; sp < splits; sp += 64) {
+      const uint64_t v = part_key[(int64_t)sp * n_nodes + b];
       key = v > key ? v : key;
     }
+    key = kcd::wave_max_u64(key);
+    if (lane != 0) return;
     const float v = key ? __uint_as_float((uint32_t)(key >> 32)) : 0.0f;
     const uint32_t idx = key ? ~(uint32_t)(key & 0xffffffffu) : 0u;
-    if (val_raw) val_raw[i] = v;
-    if (argmax) argmax[i] = (int64_t)idx;
+    if (val_raw) val_raw[b] = v;
+    if (argmax) argmax[b] = (int64_t)idx;
     if (val_bound) {
       const double vd = (double)v;
       double r;
@@ -80,26 +86,30 @@ __global__ void k_bound_finalize(const uint64_t *part_key, int n_nodes, int spli
       } else {
         r = vd * (1.0 + rel) + abs_;
       }
-      val_bound[i] = r;
+      val_bound[b] = r;
     }
-  }
-  if (cand && i < n_boxes) {
+  } else {
+    const int i = b - n_nodes;
+    if (!cand || i >= n_boxes) return;
     uint64_t key = ~0ull;
-    for (int sp = 0; sp < splits; ++sp) {
+    for (int sp = lane; sp < splits; sp += 64) {
       const uint64_t v = part_cand[(int64_t)sp * n_boxes + i];
       key = v < key ? v : key;
     }
-    cand[i] = key == ~0ull ? -1 : (int64_t)(uint32_t)(key & 0xffffffffu);
+    key = kcd::wave_min_u64(key);
+    if (lane == 0) cand[i] = key == ~0ull ? -1 : (int64_t)(uint32_t)(key & 0xffffffffu);
   }
 }
 
-__global__ void k_obj64_finalize(const double *part_val, const uint32_t *part_idx, int n_sets,
-                                 int splits, double *obj, int64_t *argmax) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+// One wavefront per candidate set: larger value wins, then the lower index.
+__global__ __launch_bounds__(64) void k_obj64_finalize(const double *part_val,
+                                                       const uint32_t *part_idx, int n_sets,
+                                                       int splits, double *obj, int64_t *argmax) {
+  const int c = blockIdx.x, lane = threadIdx.x;
   if (c >= n_sets) return;
   double best = -1.0;
   uint32_t bi = 0xffffffffu;
-  for (int sp = 0; sp < splits; ++sp) {
+  for (int sp = lane; sp < splits; sp += 64) {
     const double v = part_val[(int64_t)sp * n_sets + c];
     const uint32_t ii = part_idx[(int64_t)sp * n_sets + c];
     if (v > best || (v == best && ii < bi)) {
@@ -107,6 +117,16 @@ __global__ void k_obj64_finalize(const double *part_val, const uint32_t *part_id
       bi = ii;
     }
   }
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) {
+    const double ov = __shfl_xor(best, m);
+    const uint32_t oi = __shfl_xor(bi, m);
+    if (ov > best || (ov == best && oi < bi)) {
+      best = ov;
+      bi = oi;
+    }
+  }
+  if (lane != 0) return;
   if (obj) obj[c] = best;
   if (argmax) argmax[c] = bi == 0xffffffffu ? -1 : (int64_t)bi;
 }
@@ -229,9 +249,9 @@ kc_status kc_launch_bound(kc_handle *h, const kc_points *p, int mode, int n_node
                KC, (int)point);
   s = kc_check_launch(h, "k_bound");
   if (s != KC_OK) return s;
-  const int fin = with_cand ? (n_nodes > n_boxes ? n_nodes : n_boxes) : n_nodes;
+  const int fin = n_nodes + (with_cand ? n_boxes : 0);
   const double rel = kc_rel_margin(p->d) + 0x1p-50;
-  k_bound_finalize<<<(fin + 255) / 256, 256, 0, st>>>(A.part_key, n_nodes, (int)splits,
+  k_bound_finalize<<<fin, 64, 0, st>>>(A.part_key, n_nodes, (int)splits,
                                                        A.part_cand, n_boxes, mode, rel,
                                                        kc_abs_margin(p->d), val_raw, val_bound,
                                                        argmax, with_cand ? cand : nullptr);
@@ -308,7 +328,7 @@ extern "C" kc_status kc_objective(kc_handle *h, const kc_points *pts, int32_t n_
   if (s != KC_OK) return kc_fail(h, s, "float64 objective launch");
   s = kc_check_launch(h, "k_obj64");
   if (s != KC_OK) return s;
-  k_obj64_finalize<<<(n_sets + 255) / 256, 256, 0, st>>>(A.part_val, A.part_idx, n_sets,
-                                                          (int)splits, obj, argmax);
+  k_obj64_finalize<<<n_sets, 64, 0, st>>>(A.part_val, A.part_idx, n_sets, (int)splits, obj,
+                                           argmax);
   return kc_check_launch(h, "k_obj64_finalize");
 }

@@ -926,7 +926,7 @@ struct Solver {
       }
       // sample reduction every i_sr passes, over the open nodes and this
       // batch. A reduction that deletes under 1% of the active samples and
-      // costs more than a tenth of a pass doubles the interval (up to
+      // costs more than a quarter of a pass doubles the interval (up to
       // 64 i_sr); any other resets it to i_sr.
       ++passes_since_sr;
       if (o.i_sr > 0 && sr_interval == 0) sr_interval = o.i_sr;
@@ -937,7 +937,7 @@ struct Solver {
         if ((s = reduce(live))) return s;
         ++sr_runs;
         const double cost = now_s() - tp;
-        if ((double)(before - act.n) < 0.01 * (double)before && cost > 0.1 * last_pass_s)
+        if ((double)(before - act.n) < 0.01 * (double)before && cost > 0.25 * last_pass_s)
           sr_interval = std::min<int64_t>(sr_interval * 2, (int64_t)o.i_sr * 64);
         else
           sr_interval = o.i_sr;
