@@ -135,6 +135,19 @@ kc_status kc_objective(kc_handle *h, const kc_points *pts, int32_t n_sets, int32
                        const float *centers, int32_t precision, double *obj,
                        int64_t *argmax, void *stream);
 
+/* Algorithm 2 (farthest first traversal) from n_trials starts at once: trial t
+ * begins at sample starts[t] and adds, k-1 times, the sample farthest (float64
+ * squared distance, lowest index on ties) from its centers so far. Every step
+ * is one float64 kc_objective launch over all trials.
+ * starts (host, [n_trials]) are sample positions in 0..n-1; ids (host, out,
+ * [n_trials][k]) receive each trial's centers in order; obj (host, out,
+ * nullable, [n_trials]) the float64 objective of eq (12) at those centers.
+ * Synchronous on `stream`; KC_EINVAL for k outside 1..64, n_trials outside
+ * 1..65535 or a start out of range; KC_ENOMEM if its small device buffers
+ * cannot be allocated. */
+kc_status kc_fft(kc_handle *h, const kc_points *pts, int32_t k, int32_t n_trials,
+                 const int64_t *starts, int64_t *ids, double *obj, void *stream);
+
 /* Algorithms 3-4 for every node at incumbent alpha (host double):
  *   center-based assignment: beta_s^k > alpha for all k != k' => s in k';
  *   sample-based assignment (only if every box of the node has refs): for all

@@ -17,7 +17,7 @@ MLP_PARAMS = 10497
 # every entry point declared in include/kc.h
 EXPORTS = [
     "kc_create", "kc_destroy", "kc_last_error", "kc_rel_margin", "kc_abs_margin",
-    "kc_lower_bound", "kc_objective", "kc_tighten", "kc_reduce", "kc_autotune",
+    "kc_lower_bound", "kc_objective", "kc_fft", "kc_tighten", "kc_reduce", "kc_autotune",
     "kc_mlp_forward", "kc_mlp_backward", "kc_mlp_loss", "kc_mlp_adam", "kc_solve",
 ]
 
@@ -85,6 +85,8 @@ def load(path: str = LIB_PATH):
     L.kc_lower_bound.argtypes = [vp, P(Points), P(Nodes), vp, vp, vp, vp, vp]
     L.kc_objective.restype = st
     L.kc_objective.argtypes = [vp, P(Points), C.c_int32, C.c_int32, vp, C.c_int32, vp, vp, vp]
+    L.kc_fft.restype = st
+    L.kc_fft.argtypes = [vp, P(Points), C.c_int32, C.c_int32, vp, vp, vp, vp]
     L.kc_tighten.restype = st
     L.kc_tighten.argtypes = [vp, P(Points), P(Nodes), C.c_double, P(Refs), vp, vp, vp, vp, vp,
                              vp, vp, vp, vp, vp]

@@ -173,6 +173,19 @@ def reduce(x, n, box_off, lo, hi, beta, alpha, ref_off=None, ref=None, idx_in=No
     return x_out, idx_out, n_out, keep
 
 
+def fft(x, n, k, starts, h: Handle | None = None):
+    """Algorithm 2 from every start in `starts` (one float64 objective launch per
+    step over all trials): returns (ids int64 [trials, k], obj float64 [trials])."""
+    h = h or handle()
+    P = points(x, n)
+    st = np.ascontiguousarray(np.asarray(starts, dtype=np.int64))
+    ids = np.zeros((len(st), k), dtype=np.int64)
+    obj = np.zeros(len(st), dtype=np.float64)
+    h.check(h.lib.kc_fft(h.ptr, C.byref(P), int(k), len(st), st.ctypes.data, ids.ctypes.data,
+                         obj.ctypes.data, _stream()), "kc_fft")
+    return ids, obj
+
+
 def autotune(x, n, box_off, lo, hi, with_cand=False, k_max=None, h: Handle | None = None) -> float:
     h = h or handle()
     P = points(x, n)

@@ -339,3 +339,19 @@ def test_autotune_picks_a_variant_and_keeps_results(kc):
     assert ms > 0
     after = kc.lower_bound(xd, len(X), *args)
     assert torch.equal(before[0], after[0]) and torch.equal(before[2], after[2])
+
+
+@pytest.mark.parametrize("n,d,k,trials,seed", [(2000, 2, 3, 20, 0), (20011, 4, 5, 8, 1),
+                                               (1, 3, 1, 1, 2), (777, 5, 8, 100, 3)])
+def test_fft_parity(kc, n, d, k, trials, seed):
+    """Algorithm 2 from many starts in one batch equals the oracle's traversal
+    from each start: same centers, same float64 objective."""
+    X = datagen.gaussian_mixture(n, d, 3, 0.1, seed)
+    X64 = X.astype(np.float64)
+    starts = np.random.default_rng(seed).integers(0, n, trials)
+    ids, obj = kc.fft(kc.to_device_soa(X), n, k, starts)
+    for t in range(trials):
+        T = oracle.fft(X64, k, int(starts[t]))
+        assert np.array_equal(ids[t], T)
+        o, _ = oracle.objective(X64, X64[T][None])
+        assert obj[t] == o[0]
