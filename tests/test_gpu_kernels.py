@@ -355,3 +355,94 @@ def test_fft_parity(kc, n, d, k, trials, seed):
         assert np.array_equal(ids[t], T)
         o, _ = oracle.objective(X64, X64[T][None])
         assert obj[t] == o[0]
+
+
+def _sibling_nodes(n_pairs, k, d, seed):
+    """Pairs of nodes as branching makes them: the second node of a pair is the
+    first with one box cut at its midpoint on one attribute."""
+    off, lo, hi = datagen.random_boxes(n_pairs, k, d, seed, wmin=0.01, wmax=0.8)
+    rng = np.random.default_rng(seed)
+    los, his = [], []
+    for p in range(n_pairs):
+        l, h = lo[p * k:(p + 1) * k].copy(), hi[p * k:(p + 1) * k].copy()
+        kk, a = rng.integers(0, k), rng.integers(0, d)
+        mid = np.float32(0.5 * (l[kk, a] + h[kk, a]))
+        l2, h2 = l.copy(), h.copy()
+        l1, h1 = l.copy(), h.copy()
+        h1[kk, a] = mid
+        l2[kk, a] = mid
+        los += [l1, l2]
+        his += [h1, h2]
+    lo2 = np.concatenate(los).astype(np.float32)
+    hi2 = np.concatenate(his).astype(np.float32)
+    off2 = (np.arange(2 * n_pairs + 1) * k).astype(np.int32)
+    return off2, lo2, hi2
+
+
+@pytest.mark.parametrize("n,d,pairs,k,seed,ordered", [(20011, 2, 16, 3, 0, False), (30000, 4, 33, 5, 1, True),
+                                                      (9000, 3, 64, 10, 2, False), (5003, 5, 7, 8, 3, True)])
+@pytest.mark.parametrize("want_cand", [False, True])
+def test_lower_bound_siblings(kc, n, d, pairs, k, seed, ordered, want_cand):
+    """Sibling children as branching makes them (all boxes shared but one):
+    values, argmax and candidates equal the oracle's per node."""
+    X = datagen.gaussian_mixture(n, d, 3, 0.1, seed)
+    if ordered:
+        X = np.ascontiguousarray(X[_morton(X)])
+    off, lo, hi = _sibling_nodes(pairs, k, d, seed)
+    X64, lo64, hi64 = X.astype(np.float64), lo.astype(np.float64), hi.astype(np.float64)
+    lb, am = oracle.lower_bound(X64, off, lo64, hi64)
+    dev = lambda a: torch.from_numpy(a).cuda()
+    lb_raw, lb_safe, am_g, cand_g = kc.lower_bound(kc.to_device_soa(X), n, dev(off), dev(lo), dev(hi),
+                                                   want_cand=want_cand)
+    lb_raw, am_g = lb_raw.cpu().numpy(), am_g.cpu().numpy()
+    g, eta = _g(kc, d)
+    assert np.all(np.abs(lb_raw - lb) <= g * lb + eta)
+    assert np.all(lb_safe.cpu().numpy() <= lb)
+    for m in range(2 * pairs):
+        beta = _beta_all(X64, lo64[off[m]:off[m + 1]], hi64[off[m]:off[m + 1]])
+        near = np.nonzero(beta >= lb[m] - 2 * (g * lb[m] + eta))[0]
+        assert am_g[m] in near
+        if len(near) == 1:
+            assert am_g[m] == am[m]
+    if want_cand:
+        cand = oracle.candidates(X64, lo64, hi64)
+        cand_g = cand_g.cpu().numpy()
+        for b in range(lo.shape[0]):
+            inside = np.all((X >= lo[b]) & (X <= hi[b]), 1)
+            if cand[b] < 0:
+                assert cand_g[b] == -1 and not inside.any()
+                continue
+            assert inside[cand_g[b]]
+            mid = 0.5 * (lo64[b] + hi64[b])
+            dist = ((X64 - mid) ** 2).sum(1)
+            dist[~inside] = np.inf
+            dmin = dist[cand[b]]
+            tol = 2 * g * dmin + 1e-6 * (1 + np.sqrt(dmin)) * max(1.0, np.abs(mid).max())
+            assert dist[cand_g[b]] <= dmin + tol
+
+
+@pytest.mark.parametrize("n,d,pairs,k,seed", [(20011, 2, 16, 3, 0), (10000, 4, 40, 5, 1)])
+def test_objective_siblings(kc, n, d, pairs, k, seed):
+    """Center sets of sibling children (all centers shared but one): the float64
+    certificate is bit-identical to the oracle and the float32 screen stays
+    above it."""
+    X = datagen.gaussian_mixture(n, d, 3, 0.1, seed)
+    rng = np.random.default_rng(seed)
+    C = []
+    for p in range(pairs):
+        c = X[rng.integers(0, n, k)]
+        c2 = c.copy()
+        c2[rng.integers(0, k)] = X[rng.integers(0, n)]
+        C += [c, c2]
+    C = np.stack(C).astype(np.float32)
+    X64 = X.astype(np.float64)
+    obj, am = oracle.objective(X64, C.astype(np.float64))
+    xd = kc.to_device_soa(X)
+    Cd = torch.from_numpy(np.ascontiguousarray(C)).cuda()
+    o64, a64 = kc.objective(xd, n, Cd, precision=64)
+    assert np.array_equal(o64.cpu().numpy(), obj)
+    assert np.array_equal(a64.cpu().numpy(), am)
+    o32, _ = kc.objective(xd, n, Cd, precision=32)
+    g, eta = _g(kc, d)
+    o32 = o32.cpu().numpy()
+    assert np.all(o32 >= obj) and np.all(o32 <= obj * (1 + 3 * g) + 3 * eta)
