@@ -23,8 +23,9 @@
  *          Refs (samples known to belong to a cluster): CSR per box,
  *          rows ref_off[b] .. ref_off[b+1]-1 of ref[r*d + a].
  * Streams  `stream` is a hipStream_t (NULL = the default stream). Every call
- *          except kc_solve and kc_autotune is stream-ordered and returns once
- *          the work is validated and enqueued; KC_OK means exactly that.
+ *          except kc_solve, kc_autotune and kc_fft is stream-ordered and
+ *          returns once the work is validated and enqueued; KC_OK means
+ *          exactly that.
  * Errors   Argument errors return KC_EINVAL synchronously with a message in
  *          kc_last_error. A launch or runtime failure returns KC_EDEVICE.
  *          No C++ exception crosses this boundary. A handle is used by one
