@@ -24,6 +24,12 @@ COMMON = [
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
     # packed FP32 instructions stay off: plain float code only
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # device code only: samples and boxes are finite (the C ABI requires it),
+    # so min / max need no NaN quieting; the IEEE mode bit is cleared and
+    # float min / max compile to single instructions. Finite arithmetic and its
+    # rounding are unchanged; host code keeps full NaN semantics.
+    "-Xarch_device", "-fno-honor-nans", "-Xarch_device", "-mno-amdgpu-ieee",
+    "-Wno-nan-infinity-disabled",
     "-Wall", "-Wno-unused-function", "-Wno-unused-result",
 ]
 

@@ -53,8 +53,12 @@ __device__ __forceinline__ float sqdist(const float *xv, const float *r, int dd,
 // S samples per lane per tile (16-byte loads when S = 4), KC boxes per chunk
 // with their aggregates in registers. With all boxes of the node in one chunk
 // the box distances of the center-based test also give the inside flags.
+// Small shapes (D * KC <= 6) hold few aggregates: ask for six wavefronts per
+// SIMD (at most 80 VGPRs) so that memory latency stays hidden.
+constexpr int tighten_min_waves(int D, int KC) { return D > 0 && D * KC <= 6 ? 6 : 1; }
+
 template <int D, int KC, int S>
-__global__ __launch_bounds__(WG) void k_tighten(TightenArgs A) {
+__global__ __launch_bounds__(WG, tighten_min_waves(D, KC)) void k_tighten(TightenArgs A) {
   constexpr int DM = D ? D : 16;
   const int dd = D ? D : A.d;
   extern __shared__ float sm[];  // boxes [k_max][2*DM] then refs [*][DM]

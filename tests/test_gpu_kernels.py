@@ -446,3 +446,18 @@ def test_objective_siblings(kc, n, d, pairs, k, seed):
     g, eta = _g(kc, d)
     o32 = o32.cpu().numpy()
     assert np.all(o32 >= obj) and np.all(o32 <= obj * (1 + 3 * g) + 3 * eta)
+
+
+def test_nan_thresholds_are_rejected(kc):
+    """Host-side argument checks keep NaN semantics (the device code is built
+    for finite values only)."""
+    X = datagen.gaussian_mixture(1000, 2, 3, 0.1, 0)
+    off, lo, hi = datagen.random_boxes(2, 3, 2, 0)
+    dev = lambda a: torch.from_numpy(a).cuda()
+    xd = kc.to_device_soa(X)
+    with pytest.raises(kc.KCError):
+        kc.tighten(xd, len(X), dev(off), dev(lo), dev(hi), float("nan"), k_max=3)
+    with pytest.raises(kc.KCError):
+        kc.reduce(xd, len(X), dev(off), dev(lo), dev(hi), float("nan"), 1.0, k_max=3)
+    out = kc.tighten(xd, len(X), dev(off), dev(lo), dev(hi), 1.0, k_max=3)
+    assert out["n_in"].shape[0] == 6
