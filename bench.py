@@ -51,9 +51,10 @@ WORKLOADS = {
 }
 
 
+# the kernel's sources and the build script (its compiler flags), relative to csrc/
 KERNEL_SOURCES = {
-    "k_tighten": ["kc_tighten.hip", "kc_device.h", "kc_internal.h"],
-    "k_bound": ["kc_bound.hip", "kc_bound_impl.h", "kc_device.h", "kc_internal.h"],
+    "k_tighten": ["kc_tighten.hip", "kc_device.h", "kc_internal.h", "../build.py"],
+    "k_bound": ["kc_bound.hip", "kc_bound_impl.h", "kc_device.h", "kc_internal.h", "../build.py"],
 }
 
 
