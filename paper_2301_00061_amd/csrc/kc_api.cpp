@@ -19,7 +19,10 @@ kc_status kc_fail(kc_handle *h, kc_status st, const char *fmt, ...) {
     va_start(ap, fmt);
     vsnprintf(buf, sizeof(buf), fmt, ap);
     va_end(ap);
-    h->err = buf;
+    try {
+      h->err = buf;
+    } catch (...) {  // no memory for the message: keep the status
+    }
   }
   return st;
 }
@@ -147,7 +150,8 @@ extern "C" kc_status kc_create(kc_handle **out, int device, const char *tune_cac
   }
   if (device < 0 || device >= nd) return KC_EINVAL;
   if (hipSetDevice(device) != hipSuccess) return KC_EDEVICE;
-  kc_handle *h = new kc_handle();
+  kc_handle *h = new (std::nothrow) kc_handle();
+  if (!h) return KC_ENOMEM;
   h->device = device;
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
@@ -160,8 +164,13 @@ extern "C" kc_status kc_create(kc_handle **out, int device, const char *tune_cac
     return KC_EDEVICE;
   }
   if (tune_cache_path && *tune_cache_path) {
-    h->tune_path = tune_cache_path;
-    kc_tune_load(h);
+    try {  // no C++ exception crosses the ABI
+      h->tune_path = tune_cache_path;
+      kc_tune_load(h);
+    } catch (...) {
+      kc_destroy(h);
+      return KC_ENOMEM;
+    }
   }
   *out = h;
   return KC_OK;
@@ -215,61 +224,63 @@ void kc_tune_save(kc_handle *h) {
 
 extern "C" kc_status kc_autotune(kc_handle *h, const kc_points *pts, const kc_nodes *nodes,
                                  int32_t with_cand, double *best_ms, void *stream) {
-  if (!h) return KC_EINVAL;
-  kc_status s = kc_validate_points(h, pts);
-  if (s != KC_OK) return s;
-  s = kc_validate_nodes(h, nodes, pts);
-  if (s != KC_OK) return s;
-  hipStream_t st = (hipStream_t)stream;
-  const int nn = nodes->n_nodes, nb = nodes->n_boxes;
-  float *raw = nullptr;
-  double *safe = nullptr;
-  int64_t *am = nullptr, *cand = nullptr;
-  if (hipMalloc(&raw, nn * sizeof(float)) != hipSuccess ||
-      hipMalloc(&safe, nn * sizeof(double)) != hipSuccess ||
-      hipMalloc(&am, nn * sizeof(int64_t)) != hipSuccess ||
-      hipMalloc(&cand, (nb > 0 ? nb : 1) * sizeof(int64_t)) != hipSuccess) {
-    (void)hipGetLastError();
+  return kc_guard(h, [&]() -> kc_status {
+    if (!h) return KC_EINVAL;
+    kc_status s = kc_validate_points(h, pts);
+    if (s != KC_OK) return s;
+    s = kc_validate_nodes(h, nodes, pts);
+    if (s != KC_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    const int nn = nodes->n_nodes, nb = nodes->n_boxes;
+    float *raw = nullptr;
+    double *safe = nullptr;
+    int64_t *am = nullptr, *cand = nullptr;
+    if (hipMalloc(&raw, nn * sizeof(float)) != hipSuccess ||
+        hipMalloc(&safe, nn * sizeof(double)) != hipSuccess ||
+        hipMalloc(&am, nn * sizeof(int64_t)) != hipSuccess ||
+        hipMalloc(&cand, (nb > 0 ? nb : 1) * sizeof(int64_t)) != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipFree(raw);
+      (void)hipFree(safe);
+      (void)hipFree(am);
+      (void)hipFree(cand);
+      return kc_fail(h, KC_ENOMEM, "autotune output buffers");
+    }
+    const bool wc = with_cand != 0;
+    std::vector<kc_tile> vars = kc_bound_variants(pts->d, wc, nodes->k_max);
+    double best = 1e30;
+    kc_tile bt = kc_default_tile(h, pts->d, wc, nn, nodes->k_max, pts->n);
+    for (const kc_tile &t : vars) {
+      float ms = 0.f;
+      double tbest = 1e30;
+      bool ok = true;
+      for (int rep = 0; rep < 4 && ok; ++rep) {
+        hipEventRecord(h->ev0, st);
+        s = kc_launch_bound(h, pts, 0, nn, nb, nodes->k_max, nodes->box_off, nodes->lo, nodes->hi,
+                            raw, safe, am, wc ? cand : nullptr, t, st);
+        hipEventRecord(h->ev1, st);
+        if (s != KC_OK) {
+          ok = false;
+          break;
+        }
+        hipEventSynchronize(h->ev1);
+        hipEventElapsedTime(&ms, h->ev0, h->ev1);
+        if (rep > 0 && ms < tbest) tbest = ms;  // first run is a warm-up
+      }
+      if (ok && tbest < best) {
+        best = tbest;
+        bt = t;
+      }
+    }
+    (void)hipStreamSynchronize(st);
     (void)hipFree(raw);
     (void)hipFree(safe);
     (void)hipFree(am);
     (void)hipFree(cand);
-    return kc_fail(h, KC_ENOMEM, "autotune output buffers");
-  }
-  const bool wc = with_cand != 0;
-  std::vector<kc_tile> vars = kc_bound_variants(pts->d, wc, nodes->k_max);
-  double best = 1e30;
-  kc_tile bt = kc_default_tile(h, pts->d, wc, nn, nodes->k_max, pts->n);
-  for (const kc_tile &t : vars) {
-    float ms = 0.f;
-    double tbest = 1e30;
-    bool ok = true;
-    for (int rep = 0; rep < 4 && ok; ++rep) {
-      hipEventRecord(h->ev0, st);
-      s = kc_launch_bound(h, pts, 0, nn, nb, nodes->k_max, nodes->box_off, nodes->lo, nodes->hi,
-                          raw, safe, am, wc ? cand : nullptr, t, st);
-      hipEventRecord(h->ev1, st);
-      if (s != KC_OK) {
-        ok = false;
-        break;
-      }
-      hipEventSynchronize(h->ev1);
-      hipEventElapsedTime(&ms, h->ev0, h->ev1);
-      if (rep > 0 && ms < tbest) tbest = ms;  // first run is a warm-up
-    }
-    if (ok && tbest < best) {
-      best = tbest;
-      bt = t;
-    }
-  }
-  (void)hipStreamSynchronize(st);
-  (void)hipFree(raw);
-  (void)hipFree(safe);
-  (void)hipFree(am);
-  (void)hipFree(cand);
-  h->err.clear();
-  h->tune[kc_tune_key(pts->d, wc, nn, nodes->k_max, pts->n)] = bt;
-  kc_tune_save(h);
-  if (best_ms) *best_ms = best;
-  return best < 1e30 ? KC_OK : kc_fail(h, KC_EDEVICE, "no variant ran");
+    h->err.clear();
+    h->tune[kc_tune_key(pts->d, wc, nn, nodes->k_max, pts->n)] = bt;
+    kc_tune_save(h);
+    if (best_ms) *best_ms = best;
+    return best < 1e30 ? KC_OK : kc_fail(h, KC_EDEVICE, "no variant ran");
+  });
 }

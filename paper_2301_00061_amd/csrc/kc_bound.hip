@@ -265,70 +265,74 @@ static std::string tune_lookup_key(const kc_points *p, const kc_nodes *m, bool c
 extern "C" kc_status kc_lower_bound(kc_handle *h, const kc_points *pts, const kc_nodes *nodes,
                                     float *lb_raw, double *lb_safe, int64_t *argmax,
                                     int64_t *cand, void *stream) {
-  if (!h) return KC_EINVAL;
-  kc_status s = kc_validate_points(h, pts);
-  if (s != KC_OK) return s;
-  s = kc_validate_nodes(h, nodes, pts);
-  if (s != KC_OK) return s;
-  KC_RETURN_IF(!lb_raw && !lb_safe && !argmax && !cand, h, KC_EINVAL, "no output requested");
-  const bool wc = cand != nullptr;
-  kc_tile t;
-  auto it = h->tune.find(tune_lookup_key(pts, nodes, wc));
-  if (it != h->tune.end())
-    t = it->second;
-  else
-    t = kc_default_tile(h, pts->d, wc, nodes->n_nodes, nodes->k_max, pts->n);
-  return kc_launch_bound(h, pts, 0, nodes->n_nodes, nodes->n_boxes, nodes->k_max, nodes->box_off,
-                         nodes->lo, nodes->hi, lb_raw, lb_safe, argmax, cand, t,
-                         (hipStream_t)stream);
+  return kc_guard(h, [&]() -> kc_status {
+    if (!h) return KC_EINVAL;
+    kc_status s = kc_validate_points(h, pts);
+    if (s != KC_OK) return s;
+    s = kc_validate_nodes(h, nodes, pts);
+    if (s != KC_OK) return s;
+    KC_RETURN_IF(!lb_raw && !lb_safe && !argmax && !cand, h, KC_EINVAL, "no output requested");
+    const bool wc = cand != nullptr;
+    kc_tile t;
+    auto it = h->tune.find(tune_lookup_key(pts, nodes, wc));
+    if (it != h->tune.end())
+      t = it->second;
+    else
+      t = kc_default_tile(h, pts->d, wc, nodes->n_nodes, nodes->k_max, pts->n);
+    return kc_launch_bound(h, pts, 0, nodes->n_nodes, nodes->n_boxes, nodes->k_max, nodes->box_off,
+                           nodes->lo, nodes->hi, lb_raw, lb_safe, argmax, cand, t,
+                           (hipStream_t)stream);
+  });
 }
 
 extern "C" kc_status kc_objective(kc_handle *h, const kc_points *pts, int32_t n_sets, int32_t k,
                                   const float *centers, int32_t precision, double *obj,
                                   int64_t *argmax, void *stream) {
-  if (!h) return KC_EINVAL;
-  kc_status s = kc_validate_points(h, pts);
-  if (s != KC_OK) return s;
-  KC_RETURN_IF(n_sets < 1, h, KC_EINVAL, "n_sets must be >= 1 (got %d)", n_sets);
-  KC_RETURN_IF(k < 1 || k > 64, h, KC_EINVAL, "k must be in [1,64] (got %d)", k);
-  KC_RETURN_IF(!centers, h, KC_EINVAL, "centers is NULL");
-  KC_RETURN_IF(precision != 32 && precision != 64, h, KC_EINVAL, "precision must be 32 or 64");
-  KC_RETURN_IF(!obj && !argmax, h, KC_EINVAL, "no output requested");
-  hipStream_t st = (hipStream_t)stream;
-  if (precision == 32) {
-    kc_tile t = n_sets <= 2 ? kc_tile{4, 1, 8} : kc_tile{2, 4, 8};
-    return kc_launch_bound(h, pts, 1, n_sets, n_sets * k, k, nullptr, centers, centers, nullptr,
-                           obj, argmax, nullptr, t, st);
-  }
-  const int DM = dmax_of(pts->d);
-  const int64_t target = (int64_t)h->n_cu * 8;
-  int64_t splits = (target + n_sets - 1) / n_sets;
-  int64_t span = (pts->n + splits - 1) / splits;
-  span = (span + WG - 1) / WG * WG;
-  splits = (pts->n + span - 1) / span;
-  KC_RETURN_IF(n_sets > 65535, h, KC_EUNSUPPORTED, "too many sets for the float64 objective");
-  const size_t vb = (size_t)splits * n_sets * sizeof(double);
-  const size_t ib = (size_t)splits * n_sets * sizeof(uint32_t);
-  void *scr = nullptr;
-  s = kc_get_scratch(h, vb + ib, &scr);
-  if (s != KC_OK) return s;
-  Obj64Args A;
-  A.x = pts->x;
-  A.n = pts->n;
-  A.ld = pts->ld;
-  A.d = pts->d;
-  A.n_sets = n_sets;
-  A.k = k;
-  A.centers = centers;
-  A.span = span;
-  A.part_val = (double *)scr;
-  A.part_idx = (uint32_t *)((char *)scr + vb);
-  const size_t lds = (size_t)k * DM * sizeof(double);
-  s = dispatch64(pts->d, A, (int)splits, lds, st);
-  if (s != KC_OK) return kc_fail(h, s, "float64 objective launch");
-  s = kc_check_launch(h, "k_obj64");
-  if (s != KC_OK) return s;
-  k_obj64_finalize<<<n_sets, 64, 0, st>>>(A.part_val, A.part_idx, n_sets, (int)splits, obj,
-                                           argmax);
-  return kc_check_launch(h, "k_obj64_finalize");
+  return kc_guard(h, [&]() -> kc_status {
+    if (!h) return KC_EINVAL;
+    kc_status s = kc_validate_points(h, pts);
+    if (s != KC_OK) return s;
+    KC_RETURN_IF(n_sets < 1, h, KC_EINVAL, "n_sets must be >= 1 (got %d)", n_sets);
+    KC_RETURN_IF(k < 1 || k > 64, h, KC_EINVAL, "k must be in [1,64] (got %d)", k);
+    KC_RETURN_IF(!centers, h, KC_EINVAL, "centers is NULL");
+    KC_RETURN_IF(precision != 32 && precision != 64, h, KC_EINVAL, "precision must be 32 or 64");
+    KC_RETURN_IF(!obj && !argmax, h, KC_EINVAL, "no output requested");
+    hipStream_t st = (hipStream_t)stream;
+    if (precision == 32) {
+      kc_tile t = n_sets <= 2 ? kc_tile{4, 1, 8} : kc_tile{2, 4, 8};
+      return kc_launch_bound(h, pts, 1, n_sets, n_sets * k, k, nullptr, centers, centers, nullptr,
+                             obj, argmax, nullptr, t, st);
+    }
+    const int DM = dmax_of(pts->d);
+    const int64_t target = (int64_t)h->n_cu * 8;
+    int64_t splits = (target + n_sets - 1) / n_sets;
+    int64_t span = (pts->n + splits - 1) / splits;
+    span = (span + WG - 1) / WG * WG;
+    splits = (pts->n + span - 1) / span;
+    KC_RETURN_IF(n_sets > 65535, h, KC_EUNSUPPORTED, "too many sets for the float64 objective");
+    const size_t vb = (size_t)splits * n_sets * sizeof(double);
+    const size_t ib = (size_t)splits * n_sets * sizeof(uint32_t);
+    void *scr = nullptr;
+    s = kc_get_scratch(h, vb + ib, &scr);
+    if (s != KC_OK) return s;
+    Obj64Args A;
+    A.x = pts->x;
+    A.n = pts->n;
+    A.ld = pts->ld;
+    A.d = pts->d;
+    A.n_sets = n_sets;
+    A.k = k;
+    A.centers = centers;
+    A.span = span;
+    A.part_val = (double *)scr;
+    A.part_idx = (uint32_t *)((char *)scr + vb);
+    const size_t lds = (size_t)k * DM * sizeof(double);
+    s = dispatch64(pts->d, A, (int)splits, lds, st);
+    if (s != KC_OK) return kc_fail(h, s, "float64 objective launch");
+    s = kc_check_launch(h, "k_obj64");
+    if (s != KC_OK) return s;
+    k_obj64_finalize<<<n_sets, 64, 0, st>>>(A.part_val, A.part_idx, n_sets, (int)splits, obj,
+                                             argmax);
+    return kc_check_launch(h, "k_obj64_finalize");
+  });
 }

@@ -7,6 +7,7 @@
 
 #include <cstdint>
 #include <map>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -80,6 +81,20 @@ kc_status kc_gather(kc_handle *h, const kc_points *p, const int64_t *ids, int co
 kc_status kc_spatial_order(kc_handle *h, const kc_points *in, const uint32_t *ids_in,
                            const float *lo, const float *hi, float *x_out, uint32_t *ids_out,
                            int64_t ld_out, hipStream_t st);
+
+// Every C entry point runs its body through kc_guard, so that no C++
+// exception crosses the ABI: host allocation failures become KC_ENOMEM, any
+// other exception KC_EDEVICE (kc_fail itself never throws).
+template <class F>
+kc_status kc_guard(kc_handle *h, F &&body) noexcept {
+  try {
+    return body();
+  } catch (const std::bad_alloc &) {
+    return kc_fail(h, KC_ENOMEM, "host memory allocation failed");
+  } catch (...) {
+    return kc_fail(h, KC_EDEVICE, "internal error");
+  }
+}
 
 #define KC_RETURN_IF(cond, h, st, ...)          \
   do {                                          \

@@ -221,61 +221,69 @@ using namespace kcm;
 
 extern "C" kc_status kc_mlp_forward(kc_handle *h, const uint16_t *w_bf16, const float *feat,
                                     int64_t rows, float *score, float *act, void *stream) {
-  if (!h) return KC_EINVAL;
-  KC_RETURN_IF(!w_bf16 || !feat || !score, h, KC_EINVAL, "w / feat / score is NULL");
-  KC_RETURN_IF(rows < 0, h, KC_EINVAL, "rows < 0");
-  if (rows == 0) return KC_OK;
-  const int64_t nb = (rows + 255) / 256;
-  KC_RETURN_IF(nb > 0x7fffffff, h, KC_EUNSUPPORTED, "too many rows");
-  k_mlp_forward<<<(unsigned)nb, 256, NP * sizeof(float), (hipStream_t)stream>>>(w_bf16, feat, rows,
-                                                                               score, act);
-  return kc_check_launch(h, "k_mlp_forward");
+  return kc_guard(h, [&]() -> kc_status {
+    if (!h) return KC_EINVAL;
+    KC_RETURN_IF(!w_bf16 || !feat || !score, h, KC_EINVAL, "w / feat / score is NULL");
+    KC_RETURN_IF(rows < 0, h, KC_EINVAL, "rows < 0");
+    if (rows == 0) return KC_OK;
+    const int64_t nb = (rows + 255) / 256;
+    KC_RETURN_IF(nb > 0x7fffffff, h, KC_EUNSUPPORTED, "too many rows");
+    k_mlp_forward<<<(unsigned)nb, 256, NP * sizeof(float), (hipStream_t)stream>>>(w_bf16, feat, rows,
+                                                                                 score, act);
+    return kc_check_launch(h, "k_mlp_forward");
+  });
 }
 
 extern "C" kc_status kc_mlp_backward(kc_handle *h, const uint16_t *w_bf16, const float *feat,
                                      const float *act, const float *dscore, int64_t rows,
                                      float *dw, void *stream) {
-  if (!h) return KC_EINVAL;
-  KC_RETURN_IF(!w_bf16 || !feat || !act || !dscore || !dw, h, KC_EINVAL, "a pointer is NULL");
-  KC_RETURN_IF(rows < 1, h, KC_EINVAL, "rows must be >= 1");
-  hipStream_t st = (hipStream_t)stream;
-  const int64_t chunk = 256;
-  const int64_t n_chunks = (rows + chunk - 1) / chunk;
-  KC_RETURN_IF(n_chunks > 65535, h, KC_EUNSUPPORTED, "too many rows for one backward call");
-  const size_t gb = (size_t)rows * 3 * NH * sizeof(float);
-  const size_t pb = (size_t)n_chunks * NP * sizeof(float);
-  void *scr = nullptr;
-  kc_status s = kc_get_scratch(h, gb + pb, &scr);
-  if (s != KC_OK) return s;
-  float *grad = (float *)scr;
-  float *part = (float *)((char *)scr + gb);
-  k_mlp_back_rows<<<(unsigned)((rows + 255) / 256), 256, NP * sizeof(float), st>>>(w_bf16, act, dscore,
-                                                                                  rows, grad);
-  if ((s = kc_check_launch(h, "k_mlp_back_rows")) != KC_OK) return s;
-  k_mlp_back_params<<<dim3((NP + 255) / 256, (unsigned)n_chunks), 256, 0, st>>>(feat, act, grad, dscore,
-                                                                                rows, chunk, part);
-  if ((s = kc_check_launch(h, "k_mlp_back_params")) != KC_OK) return s;
-  k_mlp_back_sum<<<(NP + 255) / 256, 256, 0, st>>>(part, (int)n_chunks, dw);
-  return kc_check_launch(h, "k_mlp_back_sum");
+  return kc_guard(h, [&]() -> kc_status {
+    if (!h) return KC_EINVAL;
+    KC_RETURN_IF(!w_bf16 || !feat || !act || !dscore || !dw, h, KC_EINVAL, "a pointer is NULL");
+    KC_RETURN_IF(rows < 1, h, KC_EINVAL, "rows must be >= 1");
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t chunk = 256;
+    const int64_t n_chunks = (rows + chunk - 1) / chunk;
+    KC_RETURN_IF(n_chunks > 65535, h, KC_EUNSUPPORTED, "too many rows for one backward call");
+    const size_t gb = (size_t)rows * 3 * NH * sizeof(float);
+    const size_t pb = (size_t)n_chunks * NP * sizeof(float);
+    void *scr = nullptr;
+    kc_status s = kc_get_scratch(h, gb + pb, &scr);
+    if (s != KC_OK) return s;
+    float *grad = (float *)scr;
+    float *part = (float *)((char *)scr + gb);
+    k_mlp_back_rows<<<(unsigned)((rows + 255) / 256), 256, NP * sizeof(float), st>>>(w_bf16, act, dscore,
+                                                                                    rows, grad);
+    if ((s = kc_check_launch(h, "k_mlp_back_rows")) != KC_OK) return s;
+    k_mlp_back_params<<<dim3((NP + 255) / 256, (unsigned)n_chunks), 256, 0, st>>>(feat, act, grad, dscore,
+                                                                                  rows, chunk, part);
+    if ((s = kc_check_launch(h, "k_mlp_back_params")) != KC_OK) return s;
+    k_mlp_back_sum<<<(NP + 255) / 256, 256, 0, st>>>(part, (int)n_chunks, dw);
+    return kc_check_launch(h, "k_mlp_back_sum");
+  });
 }
 
 extern "C" kc_status kc_mlp_loss(kc_handle *h, const float *score, const int32_t *grp_off,
                                  const int32_t *target, int32_t n_groups, int64_t rows,
                                  float *dscore, float *loss, void *stream) {
-  if (!h) return KC_EINVAL;
-  KC_RETURN_IF(!score || !grp_off || !target || !dscore || !loss, h, KC_EINVAL, "a pointer is NULL");
-  KC_RETURN_IF(n_groups < 1 || rows < 1, h, KC_EINVAL, "need n_groups >= 1 and rows >= 1");
-  k_mlp_loss<<<1, 256, 0, (hipStream_t)stream>>>(score, grp_off, target, n_groups, rows, dscore, loss);
-  return kc_check_launch(h, "k_mlp_loss");
+  return kc_guard(h, [&]() -> kc_status {
+    if (!h) return KC_EINVAL;
+    KC_RETURN_IF(!score || !grp_off || !target || !dscore || !loss, h, KC_EINVAL, "a pointer is NULL");
+    KC_RETURN_IF(n_groups < 1 || rows < 1, h, KC_EINVAL, "need n_groups >= 1 and rows >= 1");
+    k_mlp_loss<<<1, 256, 0, (hipStream_t)stream>>>(score, grp_off, target, n_groups, rows, dscore, loss);
+    return kc_check_launch(h, "k_mlp_loss");
+  });
 }
 
 extern "C" kc_status kc_mlp_adam(kc_handle *h, float *w32, uint16_t *w_bf16, const float *dw,
                                  float *m, float *v, int32_t step, float lr, void *stream) {
-  if (!h) return KC_EINVAL;
-  KC_RETURN_IF(!w32 || !w_bf16 || !dw || !m || !v, h, KC_EINVAL, "a pointer is NULL");
-  KC_RETURN_IF(step < 1, h, KC_EINVAL, "step must be >= 1");
-  const float c1 = (float)(1.0 - std::pow(0.9, step));
-  const float c2 = (float)(1.0 - std::pow(0.999, step));
-  k_mlp_adam<<<(NP + 255) / 256, 256, 0, (hipStream_t)stream>>>(w32, w_bf16, dw, m, v, c1, c2, lr);
-  return kc_check_launch(h, "k_mlp_adam");
+  return kc_guard(h, [&]() -> kc_status {
+    if (!h) return KC_EINVAL;
+    KC_RETURN_IF(!w32 || !w_bf16 || !dw || !m || !v, h, KC_EINVAL, "a pointer is NULL");
+    KC_RETURN_IF(step < 1, h, KC_EINVAL, "step must be >= 1");
+    const float c1 = (float)(1.0 - std::pow(0.9, step));
+    const float c2 = (float)(1.0 - std::pow(0.999, step));
+    k_mlp_adam<<<(NP + 255) / 256, 256, 0, (hipStream_t)stream>>>(w32, w_bf16, dw, m, v, c1, c2, lr);
+    return kc_check_launch(h, "k_mlp_adam");
+  });
 }

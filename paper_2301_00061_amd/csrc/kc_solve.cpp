@@ -1150,35 +1150,37 @@ struct Solver {
 
 extern "C" kc_status kc_solve(kc_handle *h, const kc_points *pts, const kc_opts *opts,
                               kc_result *res) {
-  if (!h) return KC_EINVAL;
-  kc_status s = kc_validate_points(h, pts);
-  if (s != KC_OK) return s;
-  KC_RETURN_IF(!opts || !res, h, KC_EINVAL, "opts / result is NULL");
-  KC_RETURN_IF(opts->k < 1 || opts->k > 64 || opts->k > pts->n, h, KC_EINVAL,
-               "k must be in [1, min(64, n)] (got %d)", opts->k);
-  KC_RETURN_IF(opts->batch < 1, h, KC_EINVAL, "batch must be >= 1");
-  KC_RETURN_IF(opts->fft_start < 0 || opts->fft_start >= pts->n, h, KC_EINVAL,
-               "fft_start out of range");
-  KC_RETURN_IF(!(opts->eps_rel >= 0.0 && opts->eps_rel < 1.0), h, KC_EINVAL, "eps_rel in [0,1)");
-  KC_RETURN_IF(opts->max_refs < 0 || opts->max_refs > 64, h, KC_EINVAL, "max_refs in [0,64]");
-  KC_RETURN_IF(opts->branching == 1 && !opts->mlp_w, h, KC_EINVAL, "learned branching needs mlp_w");
-  KC_RETURN_IF(opts->sb_every > 0 && (!opts->sb_feat || !opts->sb_score || !opts->sb_node || opts->sb_cap < 1),
-               h, KC_EINVAL, "strong-branching labels need their host arrays");
-  std::memset(res, 0, sizeof(*res));
-  Solver S(h, pts, opts, res);
-  const double t0 = now_s();
-  s = S.run();
-  if (s != KC_OK) {
-    (void)hipDeviceSynchronize();
-    return s;
-  }
-  res->obj = S.alpha_cert;
-  res->lb = S.global_lb();
-  res->gap = S.alpha_cert > 0 ? (S.alpha_cert - res->lb) / S.alpha_cert : 0.0;
-  for (int k = 0; k < opts->k; ++k) res->centers[k] = S.inc_ids[k];
-  res->n_active = S.act.n;
-  res->sb_rows = S.sb_rows;
-  res->sb_nodes = S.sb_nodes;
-  res->seconds = now_s() - t0;
-  return KC_OK;
+  return kc_guard(h, [&]() -> kc_status {
+    if (!h) return KC_EINVAL;
+    kc_status s = kc_validate_points(h, pts);
+    if (s != KC_OK) return s;
+    KC_RETURN_IF(!opts || !res, h, KC_EINVAL, "opts / result is NULL");
+    KC_RETURN_IF(opts->k < 1 || opts->k > 64 || opts->k > pts->n, h, KC_EINVAL,
+                 "k must be in [1, min(64, n)] (got %d)", opts->k);
+    KC_RETURN_IF(opts->batch < 1, h, KC_EINVAL, "batch must be >= 1");
+    KC_RETURN_IF(opts->fft_start < 0 || opts->fft_start >= pts->n, h, KC_EINVAL,
+                 "fft_start out of range");
+    KC_RETURN_IF(!(opts->eps_rel >= 0.0 && opts->eps_rel < 1.0), h, KC_EINVAL, "eps_rel in [0,1)");
+    KC_RETURN_IF(opts->max_refs < 0 || opts->max_refs > 64, h, KC_EINVAL, "max_refs in [0,64]");
+    KC_RETURN_IF(opts->branching == 1 && !opts->mlp_w, h, KC_EINVAL, "learned branching needs mlp_w");
+    KC_RETURN_IF(opts->sb_every > 0 && (!opts->sb_feat || !opts->sb_score || !opts->sb_node || opts->sb_cap < 1),
+                 h, KC_EINVAL, "strong-branching labels need their host arrays");
+    std::memset(res, 0, sizeof(*res));
+    Solver S(h, pts, opts, res);
+    const double t0 = now_s();
+    s = S.run();
+    if (s != KC_OK) {
+      (void)hipDeviceSynchronize();
+      return s;
+    }
+    res->obj = S.alpha_cert;
+    res->lb = S.global_lb();
+    res->gap = S.alpha_cert > 0 ? (S.alpha_cert - res->lb) / S.alpha_cert : 0.0;
+    for (int k = 0; k < opts->k; ++k) res->centers[k] = S.inc_ids[k];
+    res->n_active = S.act.n;
+    res->sb_rows = S.sb_rows;
+    res->sb_nodes = S.sb_nodes;
+    res->seconds = now_s() - t0;
+    return KC_OK;
+  });
 }

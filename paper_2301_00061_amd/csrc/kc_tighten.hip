@@ -446,81 +446,83 @@ extern "C" kc_status kc_tighten(kc_handle *h, const kc_points *pts, const kc_nod
                                 double alpha, const kc_refs *refs, float *bb_lo, float *bb_hi,
                                 uint32_t *n_in, float *asg_min, float *asg_max, uint32_t *n_asg,
                                 uint32_t *n_excl, int64_t *asg_far, int8_t *labels, void *stream) {
-  if (!h) return KC_EINVAL;
-  kc_status s = kc_validate_points(h, pts);
-  if (s != KC_OK) return s;
-  s = kc_validate_nodes(h, nodes, pts);
-  if (s != KC_OK) return s;
-  s = kc_validate_refs(h, refs, nodes);
-  if (s != KC_OK) return s;
-  KC_RETURN_IF(!bb_lo || !bb_hi || !n_in || !asg_min || !asg_max || !n_asg || !n_excl, h,
-               KC_EINVAL, "an output array is NULL");
-  KC_RETURN_IF(labels && nodes->n_nodes != 1, h, KC_EINVAL, "labels need n_nodes == 1");
-  KC_RETURN_IF(std::isnan(alpha) || alpha < 0, h, KC_EINVAL, "alpha must be >= 0");
-  hipStream_t st = (hipStream_t)stream;
-  const int d = pts->d, DM = d <= 8 ? d : 16;
-  const int kc = choose_kc(d, nodes->k_max);
-  const int n_chunks = (nodes->k_max + kc - 1) / kc;
-  const int max_refs = refs ? refs->max_per_box : 0;
-  const size_t lds = ((size_t)nodes->k_max * 2 * DM + (size_t)nodes->k_max * max_refs * DM) * 4;
-  KC_RETURN_IF(lds > h->lds_per_block, h, KC_EUNSUPPORTED, "boxes and refs of a node exceed LDS");
-  const int S = (d <= 4) ? 4 : 2;
-  const int64_t units = (int64_t)nodes->n_nodes * n_chunks;
-  const int64_t target = (int64_t)h->n_cu * 8;
-  int64_t splits = (target + units - 1) / units;
-  int64_t span = (pts->n + splits - 1) / splits;
-  span = (span + WG * S - 1) / (WG * S) * (WG * S);
-  splits = (pts->n + span - 1) / span;
-  const int64_t grid = splits * units;
-  KC_RETURN_IF(grid > 0x7fffffff, h, KC_EUNSUPPORTED, "grid too large");
-
-  const int64_t nbd = (int64_t)nodes->n_boxes * d;
-  const int64_t ni = nbd > nodes->n_boxes ? nbd : nodes->n_boxes;
-  const int64_t nmax = ni > nodes->n_nodes ? ni : nodes->n_nodes;
-  if (nmax > 0)
-    k_tighten_init<<<(nmax + 255) / 256, 256, 0, st>>>(
-        (uint32_t *)bb_lo, (uint32_t *)bb_hi, (uint32_t *)asg_min, (uint32_t *)asg_max, n_in,
-        n_asg, (uint64_t *)asg_far, nbd, nodes->n_boxes, n_excl, nodes->n_nodes);
-  s = kc_check_launch(h, "k_tighten_init");
-  if (s != KC_OK) return s;
-
-  TightenArgs A;
-  A.x = pts->x;
-  A.n = pts->n;
-  A.ld = pts->ld;
-  A.d = d;
-  A.n_nodes = nodes->n_nodes;
-  A.n_boxes = nodes->n_boxes;
-  A.k_max = nodes->k_max;
-  A.box_off = nodes->box_off;
-  A.lo = nodes->lo;
-  A.hi = nodes->hi;
-  A.ref_off = refs ? refs->ref_off : nullptr;
-  A.ref = refs ? refs->ref : nullptr;
-  A.n_refs = refs ? refs->n_refs : 0;
-  A.max_refs = max_refs;
-  A.t_center = kc_thr_gt(alpha, d);
-  A.t_sample = kc_thr_gt(4.0 * alpha, d);
-  A.t_ball = kc_thr_gt(alpha, d);
-  A.n_chunks = n_chunks;
-  A.kc = kc;
-  A.span = span;
-  A.bb_lo = (uint32_t *)bb_lo;
-  A.bb_hi = (uint32_t *)bb_hi;
-  A.asg_min = (uint32_t *)asg_min;
-  A.asg_max = (uint32_t *)asg_max;
-  A.n_in = n_in;
-  A.n_asg = n_asg;
-  A.n_excl = n_excl;
-  A.asg_far = (uint64_t *)asg_far;
-  A.labels = labels;
-  s = launch(d, kc, A, (int)grid, lds, st);
-  KC_RETURN_IF(s != KC_OK, h, s, "no tighten variant for d=%d kc=%d", d, kc);
-  s = kc_check_launch(h, "k_tighten");
-  if (s != KC_OK) return s;
-  if (nmax > 0)
-    k_tighten_decode<<<(nmax + 255) / 256, 256, 0, st>>>((uint32_t *)bb_lo, (uint32_t *)bb_hi,
-                                                         (uint32_t *)asg_min, (uint32_t *)asg_max,
-                                                         nbd, (uint64_t *)asg_far, nodes->n_boxes);
-  return kc_check_launch(h, "k_tighten_decode");
+  return kc_guard(h, [&]() -> kc_status {
+    if (!h) return KC_EINVAL;
+    kc_status s = kc_validate_points(h, pts);
+    if (s != KC_OK) return s;
+    s = kc_validate_nodes(h, nodes, pts);
+    if (s != KC_OK) return s;
+    s = kc_validate_refs(h, refs, nodes);
+    if (s != KC_OK) return s;
+    KC_RETURN_IF(!bb_lo || !bb_hi || !n_in || !asg_min || !asg_max || !n_asg || !n_excl, h,
+                 KC_EINVAL, "an output array is NULL");
+    KC_RETURN_IF(labels && nodes->n_nodes != 1, h, KC_EINVAL, "labels need n_nodes == 1");
+    KC_RETURN_IF(std::isnan(alpha) || alpha < 0, h, KC_EINVAL, "alpha must be >= 0");
+    hipStream_t st = (hipStream_t)stream;
+    const int d = pts->d, DM = d <= 8 ? d : 16;
+    const int kc = choose_kc(d, nodes->k_max);
+    const int n_chunks = (nodes->k_max + kc - 1) / kc;
+    const int max_refs = refs ? refs->max_per_box : 0;
+    const size_t lds = ((size_t)nodes->k_max * 2 * DM + (size_t)nodes->k_max * max_refs * DM) * 4;
+    KC_RETURN_IF(lds > h->lds_per_block, h, KC_EUNSUPPORTED, "boxes and refs of a node exceed LDS");
+    const int S = (d <= 4) ? 4 : 2;
+    const int64_t units = (int64_t)nodes->n_nodes * n_chunks;
+    const int64_t target = (int64_t)h->n_cu * 8;
+    int64_t splits = (target + units - 1) / units;
+    int64_t span = (pts->n + splits - 1) / splits;
+    span = (span + WG * S - 1) / (WG * S) * (WG * S);
+    splits = (pts->n + span - 1) / span;
+    const int64_t grid = splits * units;
+    KC_RETURN_IF(grid > 0x7fffffff, h, KC_EUNSUPPORTED, "grid too large");
+  
+    const int64_t nbd = (int64_t)nodes->n_boxes * d;
+    const int64_t ni = nbd > nodes->n_boxes ? nbd : nodes->n_boxes;
+    const int64_t nmax = ni > nodes->n_nodes ? ni : nodes->n_nodes;
+    if (nmax > 0)
+      k_tighten_init<<<(nmax + 255) / 256, 256, 0, st>>>(
+          (uint32_t *)bb_lo, (uint32_t *)bb_hi, (uint32_t *)asg_min, (uint32_t *)asg_max, n_in,
+          n_asg, (uint64_t *)asg_far, nbd, nodes->n_boxes, n_excl, nodes->n_nodes);
+    s = kc_check_launch(h, "k_tighten_init");
+    if (s != KC_OK) return s;
+  
+    TightenArgs A;
+    A.x = pts->x;
+    A.n = pts->n;
+    A.ld = pts->ld;
+    A.d = d;
+    A.n_nodes = nodes->n_nodes;
+    A.n_boxes = nodes->n_boxes;
+    A.k_max = nodes->k_max;
+    A.box_off = nodes->box_off;
+    A.lo = nodes->lo;
+    A.hi = nodes->hi;
+    A.ref_off = refs ? refs->ref_off : nullptr;
+    A.ref = refs ? refs->ref : nullptr;
+    A.n_refs = refs ? refs->n_refs : 0;
+    A.max_refs = max_refs;
+    A.t_center = kc_thr_gt(alpha, d);
+    A.t_sample = kc_thr_gt(4.0 * alpha, d);
+    A.t_ball = kc_thr_gt(alpha, d);
+    A.n_chunks = n_chunks;
+    A.kc = kc;
+    A.span = span;
+    A.bb_lo = (uint32_t *)bb_lo;
+    A.bb_hi = (uint32_t *)bb_hi;
+    A.asg_min = (uint32_t *)asg_min;
+    A.asg_max = (uint32_t *)asg_max;
+    A.n_in = n_in;
+    A.n_asg = n_asg;
+    A.n_excl = n_excl;
+    A.asg_far = (uint64_t *)asg_far;
+    A.labels = labels;
+    s = launch(d, kc, A, (int)grid, lds, st);
+    KC_RETURN_IF(s != KC_OK, h, s, "no tighten variant for d=%d kc=%d", d, kc);
+    s = kc_check_launch(h, "k_tighten");
+    if (s != KC_OK) return s;
+    if (nmax > 0)
+      k_tighten_decode<<<(nmax + 255) / 256, 256, 0, st>>>((uint32_t *)bb_lo, (uint32_t *)bb_hi,
+                                                           (uint32_t *)asg_min, (uint32_t *)asg_max,
+                                                           nbd, (uint64_t *)asg_far, nodes->n_boxes);
+    return kc_check_launch(h, "k_tighten_decode");
+  });
 }
