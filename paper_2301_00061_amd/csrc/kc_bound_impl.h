@@ -355,7 +355,8 @@ kc_status launch_variant(int D, int S, int NG, int KC, bool point, const BoundAr
 #define KCB_LB_VARIANTS(X) X(8, 1) X(4, 1) X(2, 1) X(4, 2) X(4, 4) X(2, 4) X(4, 8) X(2, 8) X(2, 16) X(1, 16)
 #define KCB_PT_VARIANTS(X) X(4, 1) X(2, 4) X(2, 8)
 #define KCB_CAND_VARIANTS(X) \
-  X(2, 8, 4) X(2, 4, 4) X(2, 1, 4) X(2, 4, 8) X(2, 2, 8) X(2, 1, 8) X(1, 2, 16) X(1, 1, 16) X(1, 1, 64)
+  X(2, 8, 4) X(2, 4, 4) X(2, 1, 4) X(4, 4, 4) X(4, 2, 4) X(2, 4, 8) X(2, 2, 8) X(2, 1, 8)       \
+  X(4, 2, 8) X(1, 4, 8) X(1, 2, 16) X(1, 1, 16) X(1, 1, 64)
 
 #define KCB_LB_CASE(SV, NGV) \
   if (S == SV && NG == NGV) { k_bound<DV_, SV, NGV, 0, false><<<g, b, lds, st>>>(A); return KC_OK; }

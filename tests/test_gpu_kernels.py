@@ -461,3 +461,23 @@ def test_nan_thresholds_are_rejected(kc):
         kc.reduce(xd, len(X), dev(off), dev(lo), dev(hi), float("nan"), 1.0, k_max=3)
     out = kc.tighten(xd, len(X), dev(off), dev(lo), dev(hi), 1.0, k_max=3)
     assert out["n_in"].shape[0] == 6
+
+
+@pytest.mark.parametrize("n,d,nn,k,seed", [(300000, 2, 128, 3, 0), (200000, 4, 128, 5, 1),
+                                           (100000, 3, 64, 10, 2), (100000, 5, 32, 8, 3)])
+def test_autotuned_candidate_variant_matches_default(kc, n, d, nn, k, seed):
+    """Whatever tile the autotuner keeps for the bound + candidates kernel gives
+    bit-identical values, argmax and candidates to the default tile (itself
+    checked against the oracle above)."""
+    X = datagen.gaussian_mixture(n, d, 3, 0.1, seed)
+    X = np.ascontiguousarray(X[_morton(X)])
+    off, lo, hi = datagen.random_boxes(nn, k, d, seed, wmin=0.01, wmax=0.8)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    xd = kc.to_device_soa(X)
+    h = kc.Handle(0)
+    args = (dev(off), dev(lo), dev(hi))
+    before = kc.lower_bound(xd, n, *args, want_cand=True, h=h)
+    assert kc.autotune(xd, n, *args, with_cand=True, h=h) > 0
+    after = kc.lower_bound(xd, n, *args, want_cand=True, h=h)
+    for a, b in zip(before, after):
+        assert torch.equal(a, b)
