@@ -145,3 +145,20 @@ def test_spatial_order_keeps_the_certified_optimum():
     for r in (a, b):
         obj, _ = oracle.objective(X64, X64[r["centers"]][None])
         assert obj[0] == r["obj"] and r["lb"] <= r["obj"]
+
+
+@pytest.mark.parametrize("d,n", [(5, 600), (9, 500), (12, 400), (16, 300)])
+def test_solve_higher_dimensions(d, n):
+    """Beyond four attributes (and beyond eight, where the kernels take the
+    attribute count at run time) the certified optimum is the oracle's."""
+    from paper_2301_00061_amd import api
+    X = datagen.gaussian_mixture(n, d, 3, 0.08, 40 + d)
+    X64 = X.astype(np.float64)
+    opt = oracle.solve(X64, 3)
+    assert opt["status"] == 0
+    r = api.solve(api.to_device_soa(X), n, 3, batch=16, i_sr=2)
+    assert r["status"] == 0
+    assert abs(r["obj"] - opt["obj"]) <= 1e-6 * opt["obj"]
+    assert r["lb"] <= opt["obj"] * (1 + 1e-12)
+    obj, _ = oracle.objective(X64, X64[r["centers"]][None])
+    assert obj[0] == r["obj"]
