@@ -176,6 +176,9 @@ static bool cand_compiled(int S, int NG, int KC) {
 // 32 of them (NG = 32 / KC nodes per workgroup, fewer for small batches).
 static kc_tile cand_default(int n_nodes, int k_max) {
   const int kc = cand_kc(k_max);
+  // 5..8 boxes: four samples per lane and two nodes per workgroup (the
+  // autotuner's choice on batched children at D = 4, K = 5)
+  if (kc == 8 && n_nodes >= 2) return {4, 2, 8};
   int ng = kc >= 64 ? 1 : 32 / kc;
   while (ng > 1 && ng / 2 >= n_nodes) ng /= 2;
   while (ng > 1 && !cand_compiled(kc >= 16 ? 1 : 2, ng, kc)) ng /= 2;
