@@ -50,6 +50,44 @@ __device__ __forceinline__ float sqdist(const float *xv, const float *r, int dd,
   return acc;
 }
 
+// Squared distances from x to the nearest point and to the farthest corner of
+// the box [b[2a], b[2a+1]], in the same operation order as sqdist. Rounding is
+// monotone, so for every point r of the box the computed sqdist(x, r) lies
+// between the two: a threshold test that the bounding box of a set of refs
+// settles gives the same answer as testing each ref.
+__device__ __forceinline__ float box_near(const float *xv, const float *b, int dd, int DM) {
+  float acc = 0.f;
+  for (int a = 0; a < DM; ++a) {
+    if (a < dd) {
+      const float t = xv[a] - kcd::med3(b[2 * a], xv[a], b[2 * a + 1]);
+      acc = (a == 0) ? t * t : __builtin_fmaf(t, t, acc);
+    }
+  }
+  return acc;
+}
+__device__ __forceinline__ float box_far(const float *xv, const float *b, int dd, int DM) {
+  float acc = 0.f;
+  for (int a = 0; a < DM; ++a) {
+    if (a < dd) {
+      const float t = fmaxf(xv[a] - b[2 * a], b[2 * a + 1] - xv[a]);
+      acc = (a == 0) ? t * t : __builtin_fmaf(t, t, acc);
+    }
+  }
+  return acc;
+}
+
+// True when every one of the `cnt` refs at r lies within squared distance t of
+// x. The refs' bounding box settles most samples; the scan stops at the first
+// ref farther than t (refs extreme in some attribute come first).
+__device__ __forceinline__ bool all_refs_within(const float *xv, const float *rbox, const float *r,
+                                                int cnt, float t, int dd, int DM) {
+  if (box_near(xv, rbox, dd, DM) > t) return false;
+  if (box_far(xv, rbox, dd, DM) <= t) return true;
+  for (int i = 0; i < cnt; ++i)
+    if (sqdist(xv, r + i * DM, dd, DM) > t) return false;
+  return true;
+}
+
 // S samples per lane per tile (16-byte loads when S = 4), KC boxes per chunk
 // with their aggregates in registers. With all boxes of the node in one chunk
 // the box distances of the center-based test also give the inside flags.
@@ -57,7 +95,9 @@ __device__ __forceinline__ float sqdist(const float *xv, const float *r, int dd,
 // SIMD (at most 80 VGPRs) so that memory latency stays hidden.
 constexpr int tighten_min_waves(int D, int KC) { return D > 0 && D * KC <= 6 ? 6 : 1; }
 
-template <int D, int KC, int S>
+// REFS: the node batch carries refs (sample-based assignment and the balls of
+// S_+^k); without refs none of that code is compiled in.
+template <int D, int KC, int S, bool REFS>
 __global__ __launch_bounds__(WG, tighten_min_waves(D, KC)) void k_tighten(TightenArgs A) {
   constexpr int DM = D ? D : 16;
   const int dd = D ? D : A.d;
@@ -96,7 +136,8 @@ __global__ __launch_bounds__(WG, tighten_min_waves(D, KC)) void k_tighten(Tighte
   __syncthreads();
   const int cnt = s_cnt;
   float *bx = sm;
-  float *rf = sm + A.k_max * 2 * DM;
+  float *rbx = sm + A.k_max * 2 * DM;  // bounding boxes of each box's refs
+  float *rf = rbx + A.k_max * 2 * DM;
   for (int i = tid; i < A.k_max * DM; i += WG) {
     const int k = i / DM, a = i - k * DM;
     float l = 0.f, h = 0.f;
@@ -107,7 +148,7 @@ __global__ __launch_bounds__(WG, tighten_min_waves(D, KC)) void k_tighten(Tighte
     bx[k * 2 * DM + 2 * a] = l;
     bx[k * 2 * DM + 2 * a + 1] = h;
   }
-  if (A.ref_off) {
+  if (REFS && A.ref_off) {
     // refs of box k are copied densely in box order
     for (int k = 0; k < cnt; ++k) {
       const int rb = kcd::clampi(A.ref_off[s_b0 + k], 0, A.n_refs);
@@ -115,6 +156,42 @@ __global__ __launch_bounds__(WG, tighten_min_waves(D, KC)) void k_tighten(Tighte
         const int r = i / DM, a = i - r * DM;
         rf[(s_rbeg[k] + r) * DM + a] = a < dd ? A.ref[(int64_t)(rb + r) * dd + a] : 0.f;
       }
+    }
+  }
+  if (REFS) {
+    __syncthreads();
+    // one lane per box: bounding box of its refs, then the refs holding the
+    // smallest or largest value of some attribute moved to the front
+    if (tid < cnt) {
+      float *R = rf + s_rbeg[tid] * DM;
+      float *B = rbx + tid * 2 * DM;
+      const int rc = s_rcnt[tid];
+      for (int a = 0; a < DM; ++a) {
+        float l = INFINITY, h = -INFINITY;
+        for (int r = 0; r < rc; ++r) {
+          l = fminf(l, R[r * DM + a]);
+          h = fmaxf(h, R[r * DM + a]);
+        }
+        B[2 * a] = l;
+        B[2 * a + 1] = h;
+      }
+      int front = 0;
+      for (int a = 0; a < dd && front < rc; ++a)
+        for (int side = 0; side < 2 && front < rc; ++side) {
+          const float ext = side == 0 ? B[2 * a] : B[2 * a + 1];
+          bool have = false;  // an earlier front ref already holds the extreme
+          for (int r = 0; r < front; ++r) have = have || R[r * DM + a] == ext;
+          if (have) continue;
+          int best = front;
+          while (best < rc && R[best * DM + a] != ext) ++best;
+          if (best == rc) continue;
+          for (int q = 0; q < DM; ++q) {
+            const float t = R[front * DM + q];
+            R[front * DM + q] = R[best * DM + q];
+            R[best * DM + q] = t;
+          }
+          ++front;
+        }
     }
   }
   __syncthreads();
@@ -262,18 +339,12 @@ __global__ __launch_bounds__(WG, tighten_min_waves(D, KC)) void k_tighten(Tighte
       // Sample-based assignment (Lemma 2), only for unassigned samples:
       // cluster k is excluded once one of its refs is farther than 4 alpha;
       // the scan stops when two clusters remain possible.
-      if (lab == -1 && allref) {
+      if (REFS && lab == -1 && allref) {
         int n_near = 0, rest_k = -1;
         for (int k = 0; k < cnt_u && n_near < 2; ++k) {
           const int rb = __builtin_amdgcn_readfirstlane(s_rbeg[k]);
           const int rc = __builtin_amdgcn_readfirstlane(s_rcnt[k]);
-          bool fr = false;
-          for (int r = 0; r < rc; ++r)
-            if (sqdist(xv, rf + (rb + r) * DM, dd, DM) > A.t_sample) {
-              fr = true;
-              break;
-            }
-          if (!fr) {
+          if (all_refs_within(xv, rbx + k * 2 * DM, rf + rb * DM, rc, A.t_sample, dd, DM)) {
             ++n_near;
             rest_k = k;
           }
@@ -313,12 +384,8 @@ __global__ __launch_bounds__(WG, tighten_min_waves(D, KC)) void k_tighten(Tighte
           }
           // S_+^k: inside box k and within the ball of every ref of box k.
           bool in = (inm[i] >> (single ? k : kk)) & 1u;
-          if (in)
-            for (int r = 0; r < rc; ++r)
-              if (!(sqdist(xv, rf + (rb + r) * DM, dd, DM) <= A.t_ball)) {
-                in = false;
-                break;
-              }
+          if (REFS && in && rc > 0)
+            in = all_refs_within(xv, rbx + k * 2 * DM, rf + rb * DM, rc, A.t_ball, dd, DM);
           if (in) {
             ++nin[kk];
 #pragma unroll
@@ -407,7 +474,10 @@ __global__ void k_tighten_decode(uint32_t *a, uint32_t *b, uint32_t *c, uint32_t
 #define KCT_S(DV) ((DV) > 0 && (DV) <= 4 ? 4 : 2)
 #define KCT_CASE(DV, KCV)                                                      \
   if (d == DV && kc == KCV) {                                                  \
-    k_tighten<DV, KCV, KCT_S(DV)><<<grid, WG, lds, st>>>(A);                   \
+    if (refs)                                                                  \
+      k_tighten<DV, KCV, KCT_S(DV), true><<<grid, WG, lds, st>>>(A);           \
+    else                                                                       \
+      k_tighten<DV, KCV, KCT_S(DV), false><<<grid, WG, lds, st>>>(A);          \
     return KC_OK;                                                              \
   }
 #define KCT_D(DV) \
@@ -415,11 +485,20 @@ __global__ void k_tighten_decode(uint32_t *a, uint32_t *b, uint32_t *c, uint32_t
 
 static const int kKC[] = {1, 2, 3, 4, 5, 6, 8};
 
-static kc_status launch(int d, int kc, const TightenArgs &A, int grid, size_t lds, hipStream_t st) {
+static kc_status launch(int d, int kc, bool refs, const TightenArgs &A, int grid, size_t lds,
+                        hipStream_t st) {
   KCT_D(1) KCT_D(2) KCT_D(3) KCT_D(4) KCT_D(5) KCT_D(6) KCT_D(7) KCT_D(8)
   if (d > 8) {
-    if (kc == 1) { k_tighten<0, 1, 2><<<grid, WG, lds, st>>>(A); return KC_OK; }
-    if (kc == 2) { k_tighten<0, 2, 2><<<grid, WG, lds, st>>>(A); return KC_OK; }
+    if (kc == 1) {
+      if (refs) k_tighten<0, 1, 2, true><<<grid, WG, lds, st>>>(A);
+      else k_tighten<0, 1, 2, false><<<grid, WG, lds, st>>>(A);
+      return KC_OK;
+    }
+    if (kc == 2) {
+      if (refs) k_tighten<0, 2, 2, true><<<grid, WG, lds, st>>>(A);
+      else k_tighten<0, 2, 2, false><<<grid, WG, lds, st>>>(A);
+      return KC_OK;
+    }
   }
   return KC_EUNSUPPORTED;
 }
@@ -463,7 +542,7 @@ extern "C" kc_status kc_tighten(kc_handle *h, const kc_points *pts, const kc_nod
     const int kc = choose_kc(d, nodes->k_max);
     const int n_chunks = (nodes->k_max + kc - 1) / kc;
     const int max_refs = refs ? refs->max_per_box : 0;
-    const size_t lds = ((size_t)nodes->k_max * 2 * DM + (size_t)nodes->k_max * max_refs * DM) * 4;
+    const size_t lds = ((size_t)nodes->k_max * 4 * DM + (size_t)nodes->k_max * max_refs * DM) * 4;
     KC_RETURN_IF(lds > h->lds_per_block, h, KC_EUNSUPPORTED, "boxes and refs of a node exceed LDS");
     const int S = (d <= 4) ? 4 : 2;
     const int64_t units = (int64_t)nodes->n_nodes * n_chunks;
@@ -515,7 +594,7 @@ extern "C" kc_status kc_tighten(kc_handle *h, const kc_points *pts, const kc_nod
     A.n_excl = n_excl;
     A.asg_far = (uint64_t *)asg_far;
     A.labels = labels;
-    s = launch(d, kc, A, (int)grid, lds, st);
+    s = launch(d, kc, A.ref_off != nullptr, A, (int)grid, lds, st);
     KC_RETURN_IF(s != KC_OK, h, s, "no tighten variant for d=%d kc=%d", d, kc);
     s = kc_check_launch(h, "k_tighten");
     if (s != KC_OK) return s;
