@@ -173,6 +173,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="mixture_10m_d4_k5", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--node-sr", type=int, default=0,
+                    help="one-node sample reductions for nodes over at least this many samples "
+                         "(0 = off)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; the sample-sharded multi-GPU path is a "
@@ -194,7 +197,8 @@ def main() -> int:
     torch.cuda.synchronize()
     h = api.handle()
     n, k, d = W["n"], W["k"], W["d"]
-    opts = dict(batch=W["batch"], i_sr=W["i_sr"], max_nodes=W["passes"] * W["batch"] if W["passes"] else 0)
+    opts = dict(batch=W["batch"], i_sr=W["i_sr"], max_nodes=W["passes"] * W["batch"] if W["passes"] else 0,
+                node_sr=args.node_sr)
 
     # one plain device copy of the points (known size: read and write
     # d * ld * 4 bytes), untimed: scales the profiler's HBM byte counters
@@ -260,7 +264,8 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "d": d, "k": k,
                    "batch_nodes": W["batch"], "passes_per_step": W["passes"],
-                   "sample_reduction_every": W["i_sr"], "nodes_per_step": r0["nodes"],
+                   "sample_reduction_every": W["i_sr"], "node_sr": args.node_sr,
+                   "node_sr_kept": r0["node_sr_kept"], "nodes_per_step": r0["nodes"],
                    "gap_after_step": r0["gap"], "incumbent": r0["obj"],
                    "certified_optimal": r0["status"] == 0, "solve_seconds": r0["seconds"],
                    "fft100_best_obj": fft100, "ub_reduction_vs_fft100": (fft100 - r0["obj"]) / fft100,

@@ -239,6 +239,14 @@ typedef struct {
                            Morton order over the root box when n >= 65536 (the
                            certified results do not depend on the order);
                            1: keep the input order                          */
+  int32_t node_sr;      /* one-node sample reductions (Section 4.2 with the
+                           node's own lower bound): a node bounded over at
+                           least node_sr samples may get a sample set of its
+                           own, kept by its whole subtree, when that deletes
+                           at least a quarter of them. Tries are budgeted by
+                           counted work, so runs repeat exactly; 65536 suits
+                           10^6..10^9 samples; 0 = off                      */
+  int32_t reserved1;
   int64_t fft_start;    /* first FFT sample                                 */
   int64_t max_nodes;    /* 0 = unlimited                                    */
   double eps_rel;       /* relative gap at which to stop (>= 1e-6 advised)  */
@@ -277,6 +285,8 @@ typedef struct {
   int32_t status;       /* 0 closed (gap <= eps_rel), 1 node limit, 2 time limit */
   int32_t sb_rows;      /* strong-branching rows written                     */
   int32_t sb_nodes;     /* strong-branching nodes labelled                   */
+  int64_t node_sr_tries;/* one-node sample reductions run                    */
+  int64_t node_sr_kept; /* ... whose sample set a subtree kept               */
 } kc_result;
 
 /* Algorithm 1 on the device-resident samples `pts` (synchronous; uses its own

@@ -41,7 +41,8 @@ class Refs(C.Structure):
 class Opts(C.Structure):
     _fields_ = [("k", C.c_int32), ("batch", C.c_int32), ("i_sr", C.c_int32),
                 ("use_bt", C.c_int32), ("use_seeds", C.c_int32), ("max_refs", C.c_int32),
-                ("branching", C.c_int32), ("keep_order", C.c_int32), ("fft_start", C.c_int64), ("max_nodes", C.c_int64), ("eps_rel", C.c_double),
+                ("branching", C.c_int32), ("keep_order", C.c_int32), ("node_sr", C.c_int32),
+                ("reserved1", C.c_int32), ("fft_start", C.c_int64), ("max_nodes", C.c_int64), ("eps_rel", C.c_double),
                 ("time_limit_s", C.c_double), ("mlp_w", C.c_void_p), ("verbose", C.c_int32),
                 ("sb_first", C.c_int32), ("sb_every", C.c_int32), ("sb_cap", C.c_int32),
                 ("sb_feat", C.c_void_p), ("sb_score", C.c_void_p), ("sb_node", C.c_void_p)]
@@ -54,7 +55,8 @@ class Result(C.Structure):
                 ("seconds", C.c_double), ("lb_kernel_ms", C.c_double),
                 ("tighten_kernel_ms", C.c_double), ("tighten_evals", C.c_int64),
                 ("seeds_found", C.c_int32), ("status", C.c_int32), ("sb_rows", C.c_int32),
-                ("sb_nodes", C.c_int32)]
+                ("sb_nodes", C.c_int32), ("node_sr_tries", C.c_int64),
+                ("node_sr_kept", C.c_int64)]
 
 
 _lib = None

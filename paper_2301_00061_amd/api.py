@@ -238,7 +238,7 @@ def mlp_adam(w32, w_bf16, dw, m, v, step, lr, h: Handle | None = None):
 
 def solve(x, n, k, batch=64, i_sr=4, use_bt=True, use_seeds=True, max_refs=50, branching=0,
           fft_start=0, max_nodes=0, eps_rel=1e-6, time_limit_s=0.0, mlp_w=None, verbose=False,
-          sb=None, keep_order=False, h: Handle | None = None) -> dict:
+          sb=None, keep_order=False, node_sr=0, h: Handle | None = None) -> dict:
     """Algorithm 1 on device-resident samples (synchronous)."""
     h = h or handle()
     P = points(x, n)
@@ -246,7 +246,7 @@ def solve(x, n, k, batch=64, i_sr=4, use_bt=True, use_seeds=True, max_refs=50, b
              max_refs=int(max_refs), branching=int(branching), fft_start=int(fft_start),
              max_nodes=int(max_nodes), eps_rel=float(eps_rel), time_limit_s=float(time_limit_s),
              mlp_w=mlp_w.data_ptr() if mlp_w is not None else None, verbose=int(verbose),
-             keep_order=int(bool(keep_order)))
+             keep_order=int(bool(keep_order)), node_sr=int(node_sr))
     if sb is not None:
         # strong-branching label recording into host arrays (see StrongBranchingBuffer)
         o.sb_first, o.sb_every, o.sb_cap = sb.first, sb.every, sb.cap
@@ -261,7 +261,7 @@ def solve(x, n, k, batch=64, i_sr=4, use_bt=True, use_seeds=True, max_refs=50, b
                 n_active=r.n_active, seconds=r.seconds, lb_kernel_ms=r.lb_kernel_ms,
                 tighten_kernel_ms=r.tighten_kernel_ms, tighten_evals=r.tighten_evals,
                 seeds_found=bool(r.seeds_found), status=r.status, sb_rows=r.sb_rows,
-                sb_nodes=r.sb_nodes)
+                sb_nodes=r.sb_nodes, node_sr_tries=r.node_sr_tries, node_sr_kept=r.node_sr_kept)
 
 
 class StrongBranchingBuffer:

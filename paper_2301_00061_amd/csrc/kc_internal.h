@@ -30,6 +30,13 @@ struct kc_handle {
   std::string tune_path;
   std::map<std::string, kc_tile> tune;  // shape bucket -> chosen tile
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // flags and tile offsets of the last kc_reduce_count, for kc_reduce_compact
+  struct {
+    const float *x = nullptr;
+    int64_t n = 0;
+    void *scratch = nullptr;
+    size_t keep_bytes = 0, cnt_bytes = 0;
+  } red;
 };
 
 kc_status kc_fail(kc_handle *h, kc_status st, const char *fmt, ...);
@@ -73,6 +80,19 @@ void kc_tune_save(kc_handle *h);
 // Device gather of sample coordinates (kc_util.hip).
 kc_status kc_gather(kc_handle *h, const kc_points *p, const int64_t *ids, int count,
                     const uint32_t *idx_map, float *out, int64_t *orig, hipStream_t st);
+
+// Sample reduction in two phases (kc_reduce.hip; kc_reduce runs both):
+// kc_reduce_count writes the redundancy flags and tile offsets to the handle's
+// scratch and the number kept to *n_out (device); kc_reduce_compact then
+// scatters the kept samples of the same points (n_keep = that number, read
+// back by the caller) into x_out / idx_out, ld_out >= n_keep. No other call
+// on the handle may come between them.
+kc_status kc_reduce_count(kc_handle *h, const kc_points *in, const kc_nodes *open,
+                          const kc_refs *refs, double beta, double alpha, int64_t *n_out,
+                          hipStream_t st);
+kc_status kc_reduce_compact(kc_handle *h, const kc_points *in, const uint32_t *idx_in,
+                            int64_t n_keep, float *x_out, uint32_t *idx_out, int64_t ld_out,
+                            hipStream_t st);
 
 // Reorders the samples along a Morton curve over the box [lo, hi] (kc_order.hip):
 // x_out / ids_out (leading dimension ld_out) receive the samples of `in` in the

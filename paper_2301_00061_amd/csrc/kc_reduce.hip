@@ -226,6 +226,98 @@ static kc_status launch(int d, bool flags, const FlagArgs *FA, const ScatterArgs
 
 using namespace kcr;
 
+static kc_status count_impl(kc_handle *h, const kc_points *in, const kc_nodes *open,
+                            const kc_refs *refs, double beta, double alpha, uint8_t *keep,
+                            int64_t *n_out, hipStream_t st) {
+  const int64_t n_tiles = (in->n + TILE - 1) / TILE;
+  const size_t keep_bytes = keep ? 0 : (((size_t)in->n + 255) & ~(size_t)255);
+  const size_t cnt_bytes = (((size_t)n_tiles * 4) + 255) & ~(size_t)255;
+  const size_t off_bytes = (size_t)n_tiles * 8;
+  void *scr = nullptr;
+  kc_status s = kc_get_scratch(h, keep_bytes + cnt_bytes + off_bytes, &scr);
+  if (s != KC_OK) return s;
+  uint8_t *kf = keep ? keep : (uint8_t *)scr;
+  uint32_t *tcnt = (uint32_t *)((char *)scr + keep_bytes);
+  int64_t *toff = (int64_t *)((char *)scr + keep_bytes + cnt_bytes);
+
+  FlagArgs A;
+  A.x = in->x;
+  A.n = in->n;
+  A.ld = in->ld;
+  A.d = in->d;
+  A.n_nodes = open->n_nodes;
+  A.n_boxes = open->n_boxes;
+  A.k_max = open->k_max;
+  A.box_off = open->box_off;
+  A.lo = open->lo;
+  A.hi = open->hi;
+  A.ref_off = refs ? refs->ref_off : nullptr;
+  A.ref = refs ? refs->ref : nullptr;
+  A.n_refs = refs ? refs->n_refs : 0;
+  A.max_refs = refs ? refs->max_per_box : 0;
+  A.t_beta = kc_thr_lt(beta, in->d);
+  A.t_alpha = kc_thr_gt(alpha, in->d);
+  A.keep = kf;
+  A.tile_cnt = tcnt;
+  ScatterArgs SA{};
+  h->red.x = nullptr;
+  s = launch(in->d, true, &A, SA, n_tiles, st);
+  if (s != KC_OK) return kc_fail(h, s, "reduce flags launch");
+  s = kc_check_launch(h, "k_reduce_flags");
+  if (s != KC_OK) return s;
+  k_reduce_scan<<<1, 1024, 0, st>>>(tcnt, n_tiles, toff, n_out);
+  s = kc_check_launch(h, "k_reduce_scan");
+  if (s != KC_OK) return s;
+  h->red.x = in->x;
+  h->red.n = in->n;
+  h->red.scratch = scr;
+  h->red.keep_bytes = keep_bytes;
+  h->red.cnt_bytes = cnt_bytes;
+  return KC_OK;
+}
+
+// Scatter with the flags of the last count over the same points; `keep` is
+// the caller's flag array when the count wrote there.
+static kc_status compact_impl(kc_handle *h, const kc_points *in, const uint32_t *idx_in,
+                              const uint8_t *keep, float *x_out, uint32_t *idx_out, int64_t ld_out,
+                              hipStream_t st) {
+  KC_RETURN_IF(h->red.x != in->x || h->red.n != in->n || h->red.scratch != h->scratch, h,
+               KC_EINVAL, "compaction without a matching count of the same samples");
+  const int64_t n_tiles = (in->n + TILE - 1) / TILE;
+  char *scr = (char *)h->red.scratch;
+  const uint8_t *kf = keep ? keep : (const uint8_t *)scr;
+  const int64_t *toff = (const int64_t *)(scr + h->red.keep_bytes + h->red.cnt_bytes);
+  ScatterArgs SA{in->x, in->n, in->ld, in->d, idx_in, kf, toff, x_out, idx_out, ld_out};
+  h->red.x = nullptr;
+  kc_status s = launch(in->d, false, nullptr, SA, n_tiles, st);
+  if (s != KC_OK) return kc_fail(h, s, "reduce scatter launch");
+  return kc_check_launch(h, "k_reduce_scatter");
+}
+
+kc_status kc_reduce_count(kc_handle *h, const kc_points *in, const kc_nodes *open,
+                          const kc_refs *refs, double beta, double alpha, int64_t *n_out,
+                          hipStream_t st) {
+  kc_status s = kc_validate_points(h, in);
+  if (s != KC_OK) return s;
+  s = kc_validate_nodes(h, open, in);
+  if (s != KC_OK) return s;
+  s = kc_validate_refs(h, refs, open);
+  if (s != KC_OK) return s;
+  KC_RETURN_IF(!n_out, h, KC_EINVAL, "n_out is NULL");
+  KC_RETURN_IF(std::isnan(beta) || std::isnan(alpha), h, KC_EINVAL, "beta / alpha is NaN");
+  return count_impl(h, in, open, refs, beta, alpha, nullptr, n_out, st);
+}
+
+kc_status kc_reduce_compact(kc_handle *h, const kc_points *in, const uint32_t *idx_in,
+                            int64_t n_keep, float *x_out, uint32_t *idx_out, int64_t ld_out,
+                            hipStream_t st) {
+  KC_RETURN_IF(!x_out || !idx_out, h, KC_EINVAL, "x_out / idx_out is NULL");
+  KC_RETURN_IF(n_keep < 0 || n_keep > in->n || ld_out < n_keep, h, KC_EINVAL,
+               "compaction sizes (n_keep %lld, ld_out %lld)", (long long)n_keep,
+               (long long)ld_out);
+  return compact_impl(h, in, idx_in, nullptr, x_out, idx_out, ld_out, st);
+}
+
 extern "C" kc_status kc_reduce(kc_handle *h, const kc_points *in, const uint32_t *idx_in,
                                const kc_nodes *open, const kc_refs *refs, double beta,
                                double alpha, uint8_t *keep, float *x_out, uint32_t *idx_out,
@@ -242,46 +334,8 @@ extern "C" kc_status kc_reduce(kc_handle *h, const kc_points *in, const uint32_t
     KC_RETURN_IF(ld_out < in->n, h, KC_EINVAL, "ld_out < n");
     KC_RETURN_IF(std::isnan(beta) || std::isnan(alpha), h, KC_EINVAL, "beta / alpha is NaN");
     hipStream_t st = (hipStream_t)stream;
-    const int64_t n_tiles = (in->n + TILE - 1) / TILE;
-    const size_t keep_bytes = keep ? 0 : (((size_t)in->n + 255) & ~(size_t)255);
-    const size_t cnt_bytes = (((size_t)n_tiles * 4) + 255) & ~(size_t)255;
-    const size_t off_bytes = (size_t)n_tiles * 8;
-    void *scr = nullptr;
-    s = kc_get_scratch(h, keep_bytes + cnt_bytes + off_bytes, &scr);
+    s = count_impl(h, in, open, refs, beta, alpha, keep, n_out, st);
     if (s != KC_OK) return s;
-    uint8_t *kf = keep ? keep : (uint8_t *)scr;
-    uint32_t *tcnt = (uint32_t *)((char *)scr + keep_bytes);
-    int64_t *toff = (int64_t *)((char *)scr + keep_bytes + cnt_bytes);
-  
-    FlagArgs A;
-    A.x = in->x;
-    A.n = in->n;
-    A.ld = in->ld;
-    A.d = in->d;
-    A.n_nodes = open->n_nodes;
-    A.n_boxes = open->n_boxes;
-    A.k_max = open->k_max;
-    A.box_off = open->box_off;
-    A.lo = open->lo;
-    A.hi = open->hi;
-    A.ref_off = refs ? refs->ref_off : nullptr;
-    A.ref = refs ? refs->ref : nullptr;
-    A.n_refs = refs ? refs->n_refs : 0;
-    A.max_refs = refs ? refs->max_per_box : 0;
-    A.t_beta = kc_thr_lt(beta, in->d);
-    A.t_alpha = kc_thr_gt(alpha, in->d);
-    A.keep = kf;
-    A.tile_cnt = tcnt;
-    ScatterArgs SA{in->x, in->n, in->ld, in->d, idx_in, kf, toff, x_out, idx_out, ld_out};
-    s = launch(in->d, true, &A, SA, n_tiles, st);
-    if (s != KC_OK) return kc_fail(h, s, "reduce flags launch");
-    s = kc_check_launch(h, "k_reduce_flags");
-    if (s != KC_OK) return s;
-    k_reduce_scan<<<1, 1024, 0, st>>>(tcnt, n_tiles, toff, n_out);
-    s = kc_check_launch(h, "k_reduce_scan");
-    if (s != KC_OK) return s;
-    s = launch(in->d, false, &A, SA, n_tiles, st);
-    if (s != KC_OK) return kc_fail(h, s, "reduce scatter launch");
-    return kc_check_launch(h, "k_reduce_scatter");
+    return compact_impl(h, in, idx_in, keep, x_out, idx_out, ld_out, st);
   });
 }

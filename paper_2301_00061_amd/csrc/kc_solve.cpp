@@ -3,8 +3,10 @@
 // Per pass: pop up to `batch` open nodes of least lower bound; one kc_tighten
 // launch gives the assignment / tightening aggregates of all of them
 // (Algorithms 3-4) and the host forms the tightened boxes; every `i_sr` passes
-// kc_reduce deletes the samples redundant in every open node (Algorithm 5);
-// each surviving node is split (max-range rule of Section 3.3, or the learned
+// kc_reduce deletes the samples redundant in every open node (Algorithm 5),
+// and with node_sr a node may get a sample set of its own from a reduction
+// over itself alone, which its subtree inherits (nodes sharing samples are
+// launched together); each surviving node is split (max-range rule of Section 3.3, or the learned
 // rule) and one kc_lower_bound launch bounds all children and returns their
 // Section 3.2 candidates; one kc_objective launch screens the candidates in
 // float32 (rounded up); an improvement is certified in float64 over the
@@ -24,6 +26,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <vector>
 
 #include "kc_internal.h"
@@ -119,6 +122,16 @@ struct DevBuf {
   }
 };
 
+// The samples one subtree still needs: what a sample reduction over one node
+// with that node's own lower bound kept (Section 4.2: a sample redundant in a
+// node stays redundant in every node below it). The node's descendants share
+// it; when the last one leaves the tree the buffers go back to the driver's
+// pool for the next set.
+struct SampleSet {
+  DevBuf x, ids;                 // [D][ld] coordinates, [n] original ids
+  int64_t n = 0, ld = 0;
+};
+
 struct Node {
   std::vector<float> lo, hi;     // K*D (row k: lo[k*D + a])
   double lb = 0.0;               // rigorous lower bound
@@ -136,6 +149,10 @@ struct Node {
   // refs found by this node's tightening, handed to its children
   std::vector<float> new_ref;    // [K][D]
   std::vector<int64_t> new_rid;  // [K], -1 = none
+  // samples of the subtree (null: the driver's active samples), and how many
+  // more generations wait before the next one-node reduction is tried
+  std::shared_ptr<SampleSet> ss;
+  uint8_t sr_wait = 0, sr_backoff = 0;
 };
 
 struct HeapCmp {
@@ -197,6 +214,13 @@ struct Solver {
   double t_tighten = 0, t_reduce = 0, t_branch = 0, t_bound = 0;
   double last_pass_s = 0;  // wall time of the previous pass without its reduction
   int64_t sr_interval = 0, sr_runs = 0;
+  // subtree sample sets: bytes held and the cap on them; measured cost of a
+  // one-node reduction per sample of the node
+  size_t set_bytes = 0, set_cap = 0;  // held by live and pooled sets
+  int64_t last_pass_evals = 0;      // lower-bound + tightening evaluations of the last pass
+  double nsr_keep_rate[10] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 1};  // recent fraction kept per lb/alpha tenth
+  int64_t n_pass = 0, nsr_last_pass = 0;
+  std::vector<std::unique_ptr<SampleSet>> pool;
 
   Solver(kc_handle *h_, const kc_points *x, const kc_opts *op, kc_result *r)
       : h(h_), X0(x), o(*op), res(r), K(op->k), D(x->d) {
@@ -228,6 +252,48 @@ struct Solver {
   }
 
   double prune_thr() const { return alpha_ub * (1.0 - o.eps_rel); }
+
+  // Samples a node is bounded over: its subtree's set, else the active ones.
+  kc_points pts_of(const Node *m) const {
+    kc_points p = act;
+    if (m->ss) {
+      p.x = m->ss->x.as<float>();
+      p.n = m->ss->n;
+      p.ld = m->ss->ld;
+    }
+    return p;
+  }
+  const uint32_t *idx_of(const Node *m) const { return m->ss ? m->ss->ids.as<uint32_t>() : idx; }
+
+  // Maximal runs [first, last) of consecutive nodes bounded over the same
+  // samples: one launch per run.
+  static std::vector<std::pair<int, int>> runs(const std::vector<Node *> &v) {
+    std::vector<std::pair<int, int>> r;
+    for (int i = 0; i < (int)v.size();) {
+      int j = i + 1;
+      while (j < (int)v.size() && v[j]->ss == v[i]->ss) ++j;
+      r.push_back({i, j});
+      i = j;
+    }
+    return r;
+  }
+  // Stable permutation that puts nodes sharing their samples next to each
+  // other (the identity when no node has a subtree set).
+  static std::vector<int> group_order(const std::vector<Node *> &v) {
+    std::vector<const SampleSet *> first;
+    std::vector<int> key(v.size());
+    for (size_t i = 0; i < v.size(); ++i) {
+      const SampleSet *p = v[i]->ss.get();
+      size_t g = 0;
+      while (g < first.size() && first[g] != p) ++g;
+      if (g == first.size()) first.push_back(p);
+      key[i] = (int)g;
+    }
+    std::vector<int> perm(v.size());
+    for (size_t i = 0; i < v.size(); ++i) perm[i] = (int)i;
+    std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return key[a] < key[b]; });
+    return perm;
+  }
 
   void heap_push(Node *n) {
     heap.push_back(n);
@@ -466,16 +532,22 @@ struct Solver {
   // node holds no solution of objective <= a_bt.
   kc_status tighten(std::vector<Node *> &batch, std::vector<char> &alive, double a_bt) {
     const int nn = (int)batch.size();
-    std::vector<const std::vector<float> *> los(nn), his(nn);
-    std::vector<const Node *> cn(batch.begin(), batch.end());
-    for (int i = 0; i < nn; ++i) {
-      los[i] = &batch[i]->lo;
-      his[i] = &batch[i]->hi;
-    }
     const bool want_far = o.use_bt && o.max_refs > 0;
     in.reset();
     out.reset();
-    const BoxPlan P = plan_boxes(los, o.use_bt ? &cn : nullptr);
+    // one launch per run of nodes sharing their samples
+    const auto R = runs(batch);
+    std::vector<BoxPlan> plans;
+    std::vector<std::vector<const std::vector<float> *>> glo(R.size()), ghi(R.size());
+    std::vector<std::vector<const Node *>> gnode(R.size());
+    for (size_t g = 0; g < R.size(); ++g) {
+      for (int i = R[g].first; i < R[g].second; ++i) {
+        glo[g].push_back(&batch[i]->lo);
+        ghi[g].push_back(&batch[i]->hi);
+        gnode[g].push_back(batch[i]);
+      }
+      plans.push_back(plan_boxes(glo[g], o.use_bt ? &gnode[g] : nullptr));
+    }
     const size_t nbd = (size_t)nn * K * D, nb = (size_t)nn * K;
     const size_t o_bl = out.take(nbd * 4), o_bh = out.take(nbd * 4), o_am = out.take(nbd * 4),
                  o_ax = out.take(nbd * 4), o_ni = out.take(nb * 4), o_na = out.take(nb * 4),
@@ -483,25 +555,34 @@ struct Solver {
                  o_fc = out.take(nb * D * 4), o_fo = out.take(nb * 8);
     kc_status s = reserve();
     if (s) return s;
-    fill_boxes(P, los, his, o.use_bt ? &cn : nullptr);
+    for (size_t g = 0; g < R.size(); ++g) fill_boxes(plans[g], glo[g], ghi[g], o.use_bt ? &gnode[g] : nullptr);
     if ((s = upload())) return s;
-    const kc_nodes nd = dev_nodes(P);
-    const kc_refs rf = dev_refs(P);
     (void)hipEventRecord(h->ev0, st);
-    s = kc_tighten(h, &act, &nd, a_bt, P.refs ? &rf : nullptr, out.dp<float>(o_bl), out.dp<float>(o_bh),
-                   out.dp<uint32_t>(o_ni), out.dp<float>(o_am), out.dp<float>(o_ax),
-                   out.dp<uint32_t>(o_na), out.dp<uint32_t>(o_ne),
-                   want_far ? out.dp<int64_t>(o_far) : nullptr, nullptr, st);
+    for (size_t g = 0; g < R.size(); ++g) {
+      const size_t i0 = (size_t)R[g].first, gn = (size_t)(R[g].second - R[g].first);
+      const kc_points p = pts_of(batch[i0]);
+      const kc_nodes nd = dev_nodes(plans[g]);
+      const kc_refs rf = dev_refs(plans[g]);
+      s = kc_tighten(h, &p, &nd, a_bt, plans[g].refs ? &rf : nullptr, out.dp<float>(o_bl) + i0 * K * D,
+                     out.dp<float>(o_bh) + i0 * K * D, out.dp<uint32_t>(o_ni) + i0 * K,
+                     out.dp<float>(o_am) + i0 * K * D, out.dp<float>(o_ax) + i0 * K * D,
+                     out.dp<uint32_t>(o_na) + i0 * K, out.dp<uint32_t>(o_ne) + i0,
+                     want_far ? out.dp<int64_t>(o_far) + i0 * K : nullptr, nullptr, st);
+      if (s) return s;
+      res->passes++;
+      res->tighten_evals += p.n * (int64_t)gn * K;
+    }
     (void)hipEventRecord(h->ev1, st);
-    if (s) return s;
-    res->passes++;
-    res->tighten_evals += act.n * (int64_t)nn * K;
     // coordinates and original ids of the new refs, gathered before any
-    // sample reduction moves the active samples
-    if (want_far &&
-        (s = kc_gather(h, &act, out.dp<int64_t>(o_far), (int)nb, idx, out.dp<float>(o_fc),
-                       out.dp<int64_t>(o_fo), st)))
-      return s;
+    // sample reduction moves the samples
+    if (want_far)
+      for (size_t g = 0; g < R.size(); ++g) {
+        const size_t i0 = (size_t)R[g].first, gn = (size_t)(R[g].second - R[g].first);
+        const kc_points p = pts_of(batch[i0]);
+        if ((s = kc_gather(h, &p, out.dp<int64_t>(o_far) + i0 * K, (int)(gn * K), idx_of(batch[i0]),
+                           out.dp<float>(o_fc) + i0 * K * D, out.dp<int64_t>(o_fo) + i0 * K, st)))
+          return s;
+      }
     if ((s = download("tighten"))) return s;
     {
       float ms = 0.f;
@@ -572,6 +653,8 @@ struct Solver {
   }
 
   // ---------------------------------------------------- sample reduction --
+  // Over every open node, so the active samples stay valid for all of them;
+  // a subtree set no smaller than the result is then dropped.
   kc_status reduce(const std::vector<Node *> &extra) {
     std::vector<const std::vector<float> *> los, his;
     std::vector<const Node *> ns;
@@ -617,6 +700,117 @@ struct Solver {
     act.n = n_out;
     act.ld = X0->ld;
     idx = ibuf[cur].as<uint32_t>();
+    for (Node *m : heap)
+      if (m->ss && m->ss->n >= act.n) m->ss.reset();
+    for (Node *m : extra)
+      if (m->ss && m->ss->n >= act.n) m->ss.reset();
+    return KC_OK;
+  }
+
+  // Buffers for a subtree set of leading dimension ld: the smallest pooled
+  // ones that fit (and are at most 4x the need), else new ones within the cap
+  // (pooled buffers are freed first to make room). Null when over the cap.
+  std::shared_ptr<SampleSet> take_set(int64_t ld) {
+    const size_t need_x = (size_t)D * ld * 4, need_i = (size_t)ld * 4;
+    int best = -1;
+    for (int i = 0; i < (int)pool.size(); ++i) {
+      const SampleSet &q = *pool[i];
+      if (q.x.cap >= need_x && q.ids.cap >= need_i && q.x.cap <= 4 * need_x + 4096 &&
+          (best < 0 || q.x.cap < pool[best]->x.cap))
+        best = i;
+    }
+    SampleSet *raw = nullptr;
+    if (best >= 0) {
+      raw = pool[best].release();
+      pool.erase(pool.begin() + best);
+    } else {
+      const size_t bytes = need_x + need_i + 512;
+      while (set_bytes + bytes > set_cap && !pool.empty()) {
+        auto big = std::max_element(pool.begin(), pool.end(), [](const auto &a, const auto &b) {
+          return a->x.cap + a->ids.cap < b->x.cap + b->ids.cap;
+        });
+        set_bytes -= (*big)->x.cap + (*big)->ids.cap;
+        pool.erase(big);
+      }
+      if (set_bytes + bytes > set_cap) return nullptr;
+      auto fresh = std::make_unique<SampleSet>();
+      if (!fresh->x.ensure(need_x) || !fresh->ids.ensure(need_i)) return nullptr;
+      set_bytes += fresh->x.cap + fresh->ids.cap;
+      raw = fresh.release();
+    }
+    return std::shared_ptr<SampleSet>(raw, [this](SampleSet *q) { pool.emplace_back(q); });
+  }
+
+  // One-node sample reduction (Section 4.2 with the node's own lower bound
+  // as beta): the samples it deletes are redundant in every descendant, so
+  // the node's children and their subtrees are bounded over the samples it
+  // keeps. Tried only when it can pay: the node's samples number at least
+  // node_sr, some box has a half-diagonal shorter than sqrt(lb) (otherwise
+  // every point lies at least that far from a corner of every box, and no
+  // sample is redundant for the lower bound), and no box already holds more
+  // than 3/4 of the samples as center candidates. A
+  // result is kept when it deletes at least a quarter of the node's samples
+  // and fits the memory cap; a try that deletes less makes the subtree wait
+  // 1, 2, 4, ... generations before the next, a kept one 3.
+  kc_status node_reduce(Node *m, const uint32_t *nin) {
+    const kc_points p = pts_of(m);
+    if (o.node_sr <= 0 || p.n < o.node_sr || !(m->lb > 0)) return KC_OK;
+    if (m->sr_wait > 0) return KC_OK;
+    bool small = false;
+    uint32_t most = 0;
+    for (int k = 0; k < K; ++k) {
+      double r2 = 0;
+      for (int a = 0; a < D; ++a) {
+        const double hw = 0.5 * ((double)m->hi[k * D + a] - m->lo[k * D + a]);
+        r2 += hw * hw;
+      }
+      if (r2 < m->lb) small = true;
+      most = std::max(most, nin[k]);
+    }
+    if (!small || (double)most > 0.75 * (double)p.n) return KC_OK;
+    in.reset();
+    out.reset();
+    std::vector<const std::vector<float> *> los{&m->lo}, his{&m->hi};
+    std::vector<const Node *> ns{m};
+    const BoxPlan P = plan_boxes(los, o.use_bt ? &ns : nullptr);
+    const size_t o_n = out.take(8);
+    kc_status s = reserve();
+    if (s) return s;
+    fill_boxes(P, los, his, o.use_bt ? &ns : nullptr);
+    if ((s = upload())) return s;
+    // count first; only a result worth keeping is compacted, straight into
+    // buffers of its own size
+    const kc_nodes nd = dev_nodes(P);
+    const kc_refs rf = dev_refs(P);
+    s = kc_reduce_count(h, &p, &nd, P.refs ? &rf : nullptr, m->lb, alpha_ub, out.dp<int64_t>(o_n), st);
+    if (s) return s;
+    res->passes++;
+    res->node_sr_tries++;
+    const double tq = now_s();
+    if ((s = download("node reduction"))) return s;
+    const int64_t n_out = *out.hp<int64_t>(o_n);
+    if (o.verbose > 1)
+      fprintf(stderr, "[node_sr] depth %d n %lld kept %lld lb/alpha %.3f wait %.3f ms\n", m->depth,
+              (long long)p.n, (long long)n_out, m->lb / alpha_ub, (now_s() - tq) * 1e3);
+    if (n_out < 1 || (double)n_out > 0.75 * (double)p.n) {
+      // children skip 1, 2, 4, ... generations (sr_wait counts down per level)
+      m->sr_backoff = (uint8_t)std::min(m->sr_backoff + 1, 6);
+      m->sr_wait = (uint8_t)((1u << (m->sr_backoff - 1)) + 1);
+      return KC_OK;
+    }
+    const int64_t ld = (n_out + 63) / 64 * 64;
+    std::shared_ptr<SampleSet> S = take_set(ld);
+    if (!S) return KC_OK;  // over the memory cap
+    if ((s = kc_reduce_compact(h, &p, idx_of(m), n_out, S->x.as<float>(), S->ids.as<uint32_t>(), ld, st)))
+      return s;
+    S->n = n_out;
+    S->ld = ld;
+    m->ss = std::move(S);
+    // the next three generations (bounds and boxes close to this node's)
+    // keep the set as it is
+    m->sr_backoff = 0;
+    m->sr_wait = 4;
+    res->node_sr_kept++;
     return KC_OK;
   }
 
@@ -688,7 +882,7 @@ struct Solver {
       }
       mind = std::min(mind, std::sqrt(s));
     }
-    const double nact = (double)act.n, n0 = (double)X0->n;
+    const double nact = (double)(m->ss ? m->ss->n : act.n), n0 = (double)X0->n;
     const int q = k * D + a;
     const double mean_l = pc_cnt[0][q] ? pc_sum[0][q] / pc_cnt[0][q] : 0.0;
     const double mean_r = pc_cnt[1][q] ? pc_sum[1][q] / pc_cnt[1][q] : 0.0;
@@ -822,23 +1016,42 @@ struct Solver {
         }
     }
     if (cands.empty()) return KC_OK;
-    std::vector<const std::vector<float> *> los, his;
-    for (size_t c = 0; c < clo.size(); ++c) {
-      los.push_back(&clo[c]);
-      his.push_back(&chi[c]);
+    // children of nodes sharing their samples form one launch (cands are in
+    // node order, two children each)
+    std::vector<std::pair<int, int>> R;  // child ranges
+    std::vector<const Node *> rn;        // a node of each range
+    for (size_t c = 0; c < cands.size();) {
+      size_t e = c + 1;
+      while (e < cands.size() && nodes[cands[e].node]->ss == nodes[cands[c].node]->ss) ++e;
+      R.push_back({(int)(2 * c), (int)(2 * e)});
+      rn.push_back(nodes[cands[c].node]);
+      c = e;
     }
-    const int ne = (int)los.size();
+    const int ne = (int)clo.size();
     in.reset();
     out.reset();
-    const BoxPlan P = plan_boxes(los, nullptr);
+    std::vector<BoxPlan> plans;
+    std::vector<std::vector<const std::vector<float> *>> glo(R.size()), ghi(R.size());
+    for (size_t g = 0; g < R.size(); ++g) {
+      for (int j = R[g].first; j < R[g].second; ++j) {
+        glo[g].push_back(&clo[j]);
+        ghi[g].push_back(&chi[j]);
+      }
+      plans.push_back(plan_boxes(glo[g], nullptr));
+    }
     const size_t o_lb = out.take((size_t)ne * 8), o_c = out.take((size_t)ne * K * 8);
     kc_status s = reserve();
     if (s) return s;
-    fill_boxes(P, los, his, nullptr);
+    for (size_t g = 0; g < R.size(); ++g) fill_boxes(plans[g], glo[g], ghi[g], nullptr);
     if ((s = upload())) return s;
-    const kc_nodes nd = dev_nodes(P);
-    s = kc_lower_bound(h, &act, &nd, nullptr, out.dp<double>(o_lb), nullptr, out.dp<int64_t>(o_c), st);
-    if (s) return s;
+    for (size_t g = 0; g < R.size(); ++g) {
+      const size_t j0 = (size_t)R[g].first;
+      const kc_points p = pts_of(rn[g]);
+      const kc_nodes nd = dev_nodes(plans[g]);
+      s = kc_lower_bound(h, &p, &nd, nullptr, out.dp<double>(o_lb) + j0, nullptr,
+                         out.dp<int64_t>(o_c) + j0 * K, st);
+      if (s) return s;
+    }
     if ((s = download("strong branching"))) return s;
     const double *lb = out.hp<double>(o_lb);
     const int64_t *cand = out.hp<int64_t>(o_c);
@@ -878,6 +1091,12 @@ struct Solver {
     kc_status s = root();
     if (s) return s;
     if (!o.keep_order && act.n >= (1 << 16) && (s = spatial_order())) return s;
+    if (o.node_sr > 0) {
+      // subtree sets may hold up to half of the memory free now
+      size_t fr = 0, tot = 0;
+      if (hipMemGetInfo(&fr, &tot) != hipSuccess) return kc_fail(h, KC_EDEVICE, "memory info");
+      set_cap = fr / 2;
+    }
     int64_t passes_since_sr = 0;
     res->status = 0;
     std::vector<Node *> batch;
@@ -905,11 +1124,18 @@ struct Solver {
       }
       if (batch.empty()) break;
       res->nodes += (int64_t)batch.size();
+      {
+        const std::vector<int> perm = group_order(batch);
+        std::vector<Node *> b2(batch.size());
+        for (size_t i = 0; i < perm.size(); ++i) b2[i] = batch[perm[i]];
+        batch.swap(b2);
+      }
 
       // bounds tightening
       const double a_bt = o.use_bt ? alpha_ub : INFINITY;
       double tp = now_s();
       const double pass_start = tp;
+      const int64_t evals_start = res->evals + res->tighten_evals;
       double sr_cost = 0;
       if ((s = tighten(batch, alive, a_bt))) return s;
       t_tighten += now_s() - tp;
@@ -961,6 +1187,37 @@ struct Solver {
           to_branch_bidx.push_back(bidx[i]);
         }
       }
+      // one-node reductions give subtrees their own samples. A try over n
+      // samples is priced at 2 K n sample-box evaluations (redundancy tests
+      // of K boxes, scan, read-back); the tries of a pass stay within a
+      // quarter of the previous pass's evaluations, and a node is tried only
+      // while at least a quarter of the recent tries at its lb / alpha (in
+      // tenths) were kept. One try every 16 passes goes ahead regardless, so
+      // the rates can recover. Every rule counts work, not time, so runs
+      // repeat exactly.
+      ++n_pass;
+      if (o.node_sr > 0) {
+        const double tn = now_s();
+        double budget = 0.25 * (double)last_pass_evals;
+        bool force = n_pass - nsr_last_pass >= 16;
+        for (size_t i = 0; i < to_branch.size(); ++i) {
+          Node *m = to_branch[i];
+          const double cost = 2.0 * K * (double)pts_of(m).n;
+          const int bk = std::max(0, std::min(9, (int)(10.0 * m->lb / alpha_ub)));
+          if ((cost > budget || nsr_keep_rate[bk] < 0.25) && !force) continue;
+          const int64_t tries = res->node_sr_tries, kept = res->node_sr_kept;
+          if ((s = node_reduce(m, &ta.nin[(size_t)to_branch_bidx[i] * K]))) return s;
+          if (res->node_sr_tries > tries) {
+            nsr_keep_rate[bk] = 0.9 * nsr_keep_rate[bk] + (res->node_sr_kept > kept ? 0.1 : 0.0);
+            budget -= cost;
+            force = false;
+            nsr_last_pass = n_pass;
+          }
+        }
+        t_reduce += now_s() - tn;
+        sr_cost += now_s() - tn;
+        tp += now_s() - tn;
+      }
       std::vector<int> ck, ca;
       if ((s = choose(to_branch, to_branch_bidx, ck, ca))) return s;
       if (o.sb_every > 0 && o.sb_feat && o.sb_score && o.sb_node) {
@@ -1003,6 +1260,9 @@ struct Solver {
           c->nsplit = m->nsplit;
           if (c->nsplit[k * D + a] < 255) c->nsplit[k * D + a]++;
           inherit_refs(m, c);
+          c->ss = m->ss;
+          c->sr_backoff = m->sr_backoff;
+          c->sr_wait = m->sr_wait > 0 ? (uint8_t)(m->sr_wait - 1) : 0;
           c->id = next_id++;
           if (symmetry && !apply_symmetry(c->lo, c->hi)) {
             delete c;  // empty box: no solution
@@ -1023,15 +1283,18 @@ struct Solver {
         if ((s = bound(ev, is_leaf))) return s;
       t_bound += now_s() - tp;
       last_pass_s = now_s() - pass_start - sr_cost;
+      last_pass_evals = res->evals + res->tighten_evals - evals_start;
 
       if (!heap.empty()) {
         const double lb = global_lb();
         if (alpha_cert - lb <= o.eps_rel * alpha_cert) break;
       }
       if (o.verbose && (res->nodes % (o.batch * 20) < o.batch))
-        fprintf(stderr, "[kc_solve] nodes %lld open %zu n_active %lld alpha %.9g lb %.9g t %.2fs\n",
-                (long long)res->nodes, heap.size(), (long long)act.n, alpha_cert, global_lb(),
-                now_s() - t0);
+        fprintf(stderr,
+                "[kc_solve] nodes %lld open %zu n_active %lld subtree sets %.3f GB alpha %.9g lb %.9g "
+                "t %.2fs\n",
+                (long long)res->nodes, heap.size(), (long long)act.n, set_bytes * 1e-9, alpha_cert,
+                global_lb(), now_s() - t0);
     }
     if (o.verbose)
       fprintf(stderr,
@@ -1045,16 +1308,30 @@ struct Solver {
   // candidates' objective in one float32 launch (coordinates gathered on the
   // device), float64 certificate of an improvement. Children with an empty
   // box are dropped; leaves leave the tree.
-  kc_status bound(std::vector<Node *> &ev, const std::vector<char> &is_leaf) {
-    const int ne = (int)ev.size();
-    std::vector<const std::vector<float> *> los(ne), his(ne);
-    for (int i = 0; i < ne; ++i) {
-      los[i] = &ev[i]->lo;
-      his[i] = &ev[i]->hi;
+  kc_status bound(std::vector<Node *> &ev_in, const std::vector<char> &leaf_in) {
+    const int ne = (int)ev_in.size();
+    // nodes sharing their samples next to each other: one launch per run
+    std::vector<Node *> ev(ne);
+    std::vector<char> is_leaf(ne);
+    {
+      const std::vector<int> perm = group_order(ev_in);
+      for (int i = 0; i < ne; ++i) {
+        ev[i] = ev_in[perm[i]];
+        is_leaf[i] = leaf_in[perm[i]];
+      }
     }
+    const auto R = runs(ev);
     in.reset();
     out.reset();
-    const BoxPlan P = plan_boxes(los, nullptr);
+    std::vector<BoxPlan> plans;
+    std::vector<std::vector<const std::vector<float> *>> glo(R.size()), ghi(R.size());
+    for (size_t g = 0; g < R.size(); ++g) {
+      for (int i = R[g].first; i < R[g].second; ++i) {
+        glo[g].push_back(&ev[i]->lo);
+        ghi[g].push_back(&ev[i]->hi);
+      }
+      plans.push_back(plan_boxes(glo[g], nullptr));
+    }
     const size_t ng = (size_t)ne * K + ne;  // candidates, then the LB samples
     const size_t o_lb = out.take((size_t)ne * 8), o_ids = out.take(ng * 8),
                  o_xy = out.take(ng * D * 4), o_orig = out.take(ng * 8),
@@ -1062,24 +1339,41 @@ struct Solver {
                  o_cert = out.take(8), o_cam = out.take(8);
     kc_status s = reserve();
     if (s) return s;
-    fill_boxes(P, los, his, nullptr);
+    for (size_t g = 0; g < R.size(); ++g) fill_boxes(plans[g], glo[g], ghi[g], nullptr);
     if ((s = upload())) return s;
-    const kc_nodes nd = dev_nodes(P);
     int64_t *ids = out.dp<int64_t>(o_ids);
+    int64_t *orig = out.dp<int64_t>(o_orig);
+    float *dxy = out.dp<float>(o_xy);
     (void)hipEventRecord(h->ev0, st);
-    s = kc_lower_bound(h, &act, &nd, nullptr, out.dp<double>(o_lb), ids + (size_t)ne * K, ids, st);
+    for (size_t g = 0; g < R.size(); ++g) {
+      const size_t i0 = (size_t)R[g].first, gn = (size_t)(R[g].second - R[g].first);
+      const kc_points p = pts_of(ev[i0]);
+      const kc_nodes nd = dev_nodes(plans[g]);
+      s = kc_lower_bound(h, &p, &nd, nullptr, out.dp<double>(o_lb) + i0, ids + (size_t)ne * K + i0,
+                         ids + i0 * K, st);
+      if (s) return s;
+      res->passes++;
+      res->evals += p.n * (int64_t)gn * K;
+    }
     (void)hipEventRecord(h->ev1, st);
-    if (s) return s;
-    res->passes++;
-    res->evals += act.n * (int64_t)ne * K;
-    if ((s = kc_gather(h, &act, ids, (int)ng, idx, out.dp<float>(o_xy), out.dp<int64_t>(o_orig), st)))
-      return s;
-    // the objective of every candidate set (a set with an empty box reads
-    // sample 0 in its place; its value is never used)
-    s = kc_objective(h, &act, ne, K, out.dp<float>(o_xy), 32, out.dp<double>(o_obj),
-                     out.dp<int64_t>(o_oam), st);
-    if (s) return s;
-    res->passes++;
+    for (size_t g = 0; g < R.size(); ++g) {
+      const size_t i0 = (size_t)R[g].first, gn = (size_t)(R[g].second - R[g].first);
+      const kc_points p = pts_of(ev[i0]);
+      const uint32_t *ix = idx_of(ev[i0]);
+      if ((s = kc_gather(h, &p, ids + i0 * K, (int)(gn * K), ix, dxy + i0 * K * D, orig + i0 * K, st)))
+        return s;
+      if ((s = kc_gather(h, &p, ids + (size_t)ne * K + i0, (int)gn, ix, dxy + ((size_t)ne * K + i0) * D,
+                         orig + (size_t)ne * K + i0, st)))
+        return s;
+      // the objective of every candidate set (a set with an empty box reads
+      // sample 0 in its place; its value is never used); over the node's
+      // samples it equals the objective over all samples, since a deleted
+      // sample lies closer than the node's bound to any centers in its boxes
+      s = kc_objective(h, &p, (int)gn, K, dxy + i0 * K * D, 32, out.dp<double>(o_obj) + i0,
+                       out.dp<int64_t>(o_oam) + i0, st);
+      if (s) return s;
+      res->passes++;
+    }
     if ((s = download("bound"))) return s;
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, h->ev0, h->ev1);
@@ -1087,7 +1381,7 @@ struct Solver {
     const double *lb = out.hp<double>(o_lb);
     const int64_t *cand = out.hp<int64_t>(o_ids);
     const float *xy = out.hp<float>(o_xy);
-    const int64_t *orig = out.hp<int64_t>(o_orig);
+    const int64_t *horig = out.hp<int64_t>(o_orig);
     const double *ub = out.hp<double>(o_obj);
 
     std::vector<char> ok(ne, 1);
@@ -1110,7 +1404,7 @@ struct Solver {
       if ((s = sync("certificate"))) return s;
       if (cert < alpha_cert) {
         alpha_cert = cert;
-        inc_ids.assign(orig + (size_t)best * K, orig + (size_t)best * K + K);
+        inc_ids.assign(horig + (size_t)best * K, horig + (size_t)best * K + K);
         inc_coords.assign(xy + (size_t)best * K * D, xy + (size_t)best * K * D + K * D);
       }
       alpha_ub = std::min(alpha_ub, alpha_cert);
@@ -1162,6 +1456,7 @@ extern "C" kc_status kc_solve(kc_handle *h, const kc_points *pts, const kc_opts 
                  "fft_start out of range");
     KC_RETURN_IF(!(opts->eps_rel >= 0.0 && opts->eps_rel < 1.0), h, KC_EINVAL, "eps_rel in [0,1)");
     KC_RETURN_IF(opts->max_refs < 0 || opts->max_refs > 64, h, KC_EINVAL, "max_refs in [0,64]");
+    KC_RETURN_IF(opts->node_sr < 0, h, KC_EINVAL, "node_sr must be >= 0");
     KC_RETURN_IF(opts->branching == 1 && !opts->mlp_w, h, KC_EINVAL, "learned branching needs mlp_w");
     KC_RETURN_IF(opts->sb_every > 0 && (!opts->sb_feat || !opts->sb_score || !opts->sb_node || opts->sb_cap < 1),
                  h, KC_EINVAL, "strong-branching labels need their host arrays");

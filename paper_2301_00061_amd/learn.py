@@ -187,7 +187,7 @@ def shifted_geomean(ts, shift=1.0):
     return math.exp(sum(math.log(t + shift) for t in ts) / len(ts)) - shift
 
 
-def evaluate(seeds, n, k, wb, time_limit, batch=64):
+def evaluate(seeds, n, k, wb, time_limit, batch=64, node_sr=0):
     rows = []
     for seed in seeds:
         x, kk = datagen.learned_instance_device(seed, n, k=k)
@@ -196,7 +196,7 @@ def evaluate(seeds, n, k, wb, time_limit, batch=64):
         for rule in ("plain", "learned"):
             r = api.solve(x, n, kk, batch=batch, i_sr=2, time_limit_s=time_limit,
                           branching=1 if rule == "learned" else 0,
-                          mlp_w=wb if rule == "learned" else None)
+                          mlp_w=wb if rule == "learned" else None, node_sr=node_sr)
             res[rule] = dict(seconds=r["seconds"], nodes=r["nodes"], gap=r["gap"],
                              solved=r["status"] == 0, obj=r["obj"])
         rows.append(dict(seed=seed, k=kk, n=n, **res))
@@ -229,6 +229,8 @@ def main(argv=None):
     ap.add_argument("--eval-k", type=int, default=0)
     ap.add_argument("--time-limit", type=float, default=30.0)
     ap.add_argument("--report", default=None)
+    ap.add_argument("--node-sr", type=int, default=0,
+                    help="one-node sample reductions for nodes over at least this many samples")
     a = ap.parse_args(argv)
     torch.cuda.set_device(0)
     report = {}
@@ -250,9 +252,10 @@ def main(argv=None):
     else:
         wb, meta = load(a.weights)
     lo, hi = (int(v) for v in a.eval_seeds.split(":"))
-    rows, summ = evaluate(range(lo, hi), a.eval_n, a.eval_k or None, wb, a.time_limit)
+    rows, summ = evaluate(range(lo, hi), a.eval_n, a.eval_k or None, wb, a.time_limit,
+                          node_sr=a.node_sr)
     report["eval"] = dict(rows=rows, summary=summ, n=a.eval_n, k=a.eval_k or "U{4..8}",
-                          time_limit=a.time_limit)
+                          time_limit=a.time_limit, node_sr=a.node_sr)
     log("[eval] summary " + json.dumps(summ))
     if a.report:
         with open(a.report, "w") as f:

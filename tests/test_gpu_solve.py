@@ -86,7 +86,8 @@ def test_solve_one_dimensional(kc):
 
 @pytest.mark.parametrize("opts", [dict(use_bt=False, i_sr=0), dict(i_sr=0), dict(use_seeds=False),
                                   dict(batch=1), dict(batch=256, i_sr=1), dict(max_refs=0),
-                                  dict(max_refs=1)])
+                                  dict(max_refs=1), dict(node_sr=1), dict(node_sr=1, batch=1),
+                                  dict(node_sr=1, i_sr=0), dict(node_sr=1, use_seeds=False)])
 def test_solve_variants_agree(kc, opts):
     X = datagen.small_mixture(2)
     X64 = X.astype(np.float64)
@@ -129,6 +130,8 @@ def test_solve_rejects_bad_arguments(kc):
         kc.solve(xd, len(X), 3, fft_start=len(X))
     with pytest.raises(kc.KCError):
         kc.solve(xd, len(X), 3, batch=0)
+    with pytest.raises(kc.KCError):
+        kc.solve(xd, len(X), 3, node_sr=-1)
 
 
 def test_spatial_order_keeps_the_certified_optimum():
@@ -162,3 +165,37 @@ def test_solve_higher_dimensions(d, n):
     assert r["lb"] <= opt["obj"] * (1 + 1e-12)
     obj, _ = oracle.objective(X64, X64[r["centers"]][None])
     assert obj[0] == r["obj"]
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_node_reduction_medium_instances(kc, seed):
+    """One-node sample reductions (each subtree bounded over the samples its
+    root node kept): the oracle's certified optimum, with subtree sets used."""
+    X = datagen.gaussian_mixture(20000, 2, 3, 0.05, seed)
+    X64 = X.astype(np.float64)
+    ro = oracle.solve(X64, 3)
+    r = kc.solve(kc.to_device_soa(X), len(X), 3, batch=32, i_sr=2, node_sr=1)
+    assert r["status"] == 0
+    _check(X64, r, ro["obj"])
+    assert r["node_sr_kept"] > 0, r
+
+
+def test_node_reduction_large_instance(kc):
+    """200,000 samples, D = 2, K = 3, subtree sets from 4,096 samples up: the
+    certified optimum of the run without them, and strong-branching rows
+    recorded from subtree sets stay finite."""
+    from paper_2301_00061_amd import api
+    X = datagen.gaussian_mixture(200_000, 2, 3, 0.05, 21)
+    X64 = X.astype(np.float64)
+    xd = kc.to_device_soa(X)
+    a = kc.solve(xd, len(X), 3, batch=64, i_sr=2, time_limit_s=60)
+    sb = api.StrongBranchingBuffer(4096, first=16, every=4)
+    b = kc.solve(xd, len(X), 3, batch=64, i_sr=2, node_sr=4096, sb=sb, time_limit_s=60)
+    assert a["status"] == 0 and b["status"] == 0
+    assert b["node_sr_kept"] > 0, b
+    assert abs(a["obj"] - b["obj"]) <= 1e-6 * a["obj"]
+    for r in (a, b):
+        obj, _ = oracle.objective(X64, X64[r["centers"]][None])
+        assert obj[0] == r["obj"] and r["lb"] <= min(a["obj"], b["obj"]) * (1 + 1e-12)
+    assert b["sb_rows"] > 0
+    assert np.all(np.isfinite(sb.feat[:b["sb_rows"]])) and np.all(sb.score[:b["sb_rows"]] > 0)

@@ -390,3 +390,48 @@ def test_planted_mistake_is_caught(orc):
         right = orc.point_box_min_dist2(x, lo, hi)
         bad += abs(wrong - right) > 1e-12
     assert bad > 0
+
+
+@pytest.mark.parametrize("seed", [0, 1, 3])
+def test_node_reduction_carries_over_to_descendants(orc, seed):
+    """Section 4.2 applied to one node with its own lower bound as beta: the
+    samples deleted there change nothing below it. For descendants reached by
+    midpoint splits, the inherited lower bound max(LB(M), LB(M')) is the same
+    over the kept samples as over all, the objective of centers inside M' is
+    the same, and so are the count and bounding box of S_+ per box."""
+    X = datagen.gaussian_mixture(600, 2, 3, 0.06, 500 + seed).astype(np.float64)
+    T = orc.fft(X, 3)
+    c = X[T]
+    lo, hi = c - 0.08, c + 0.08
+    lb_m = orc.lower_bound(X, [0, 3], lo, hi)[0][0]
+    alpha = orc.objective(X, c[None])[0][0]
+    ref_off = np.arange(4, dtype=np.int32)
+    keep = orc.reduce_flags(X, [0, 3], lo, hi, ref_off, c, lb_m, alpha).astype(bool)
+    assert 0 < keep.sum() < len(X)
+    Xk = X[keep]
+    rng = np.random.default_rng(seed)
+    checked = 0
+    for _ in range(12):
+        l2, h2 = lo.copy(), hi.copy()
+        for _depth in range(int(rng.integers(1, 7))):
+            k, a = int(rng.integers(3)), int(rng.integers(2))
+            mid = 0.5 * (l2[k, a] + h2[k, a])
+            if rng.integers(2):
+                h2[k, a] = mid
+            else:
+                l2[k, a] = mid
+        full = orc.lower_bound(X, [0, 3], l2, h2)[0][0]
+        kept = orc.lower_bound(Xk, [0, 3], l2, h2)[0][0]
+        assert max(lb_m, kept) == max(lb_m, full)
+        cand = orc.candidates(X, l2, h2)
+        if np.all(cand >= 0):
+            C = X[cand][None]
+            assert orc.objective(Xk, C)[0][0] == orc.objective(X, C)[0][0]
+            checked += 1
+        ta = orc.tighten_node(X, l2, h2, alpha, ref_off, c)
+        tk = orc.tighten_node(Xk, l2, h2, alpha, ref_off, c)
+        assert np.array_equal(ta["n_in"], tk["n_in"])
+        has = ta["n_in"] > 0
+        assert np.array_equal(ta["bb_lo"][has], tk["bb_lo"][has])
+        assert np.array_equal(ta["bb_hi"][has], tk["bb_hi"][has])
+    assert checked > 0
