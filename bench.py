@@ -40,6 +40,11 @@ WORKLOADS = {
                               batch=64, i_sr=2, passes=40),
     "mixture_1b_d2_k3": dict(n=1_000_000_000, d=2, k=3, std=0.05, outliers=0.0, seed=0,
                              batch=64, i_sr=1, passes=None),
+    # held-out instance of the learned-branching family (4 Gaussians, std 0.1,
+    # 5 attributes): solve to the certified optimum with per-node carry-over,
+    # capped at 120 s
+    "mixture_50m_d5_k4": dict(n=50_000_000, d=5, k=4, std=0.1, outliers=0.0, seed=10001,
+                              batch=64, i_sr=2, passes=None, node_sr=65536, time_limit=120.0),
     # a step is one lower-bound pass of one node (K boxes) over all samples:
     # the per-node bound evaluation itself, bound by HBM bandwidth
     "lb_1b_d2_k3": dict(n=1_000_000_000, d=2, k=3, std=0.05, outliers=0.0, seed=0,
@@ -173,9 +178,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="mixture_10m_d4_k5", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--node-sr", type=int, default=0,
+    ap.add_argument("--node-sr", type=int, default=None,
                     help="one-node sample reductions for nodes over at least this many samples "
-                         "(0 = off)")
+                         "(0 = off; default: the workload's setting)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; the sample-sharded multi-GPU path is a "
@@ -197,8 +202,9 @@ def main() -> int:
     torch.cuda.synchronize()
     h = api.handle()
     n, k, d = W["n"], W["k"], W["d"]
+    node_sr = args.node_sr if args.node_sr is not None else W.get("node_sr", 0)
     opts = dict(batch=W["batch"], i_sr=W["i_sr"], max_nodes=W["passes"] * W["batch"] if W["passes"] else 0,
-                node_sr=args.node_sr)
+                node_sr=node_sr, time_limit_s=W.get("time_limit", 0.0))
 
     # one plain device copy of the points (known size: read and write
     # d * ld * 4 bytes), untimed: scales the profiler's HBM byte counters
@@ -264,7 +270,7 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "d": d, "k": k,
                    "batch_nodes": W["batch"], "passes_per_step": W["passes"],
-                   "sample_reduction_every": W["i_sr"], "node_sr": args.node_sr,
+                   "sample_reduction_every": W["i_sr"], "node_sr": node_sr,
                    "node_sr_kept": r0["node_sr_kept"], "nodes_per_step": r0["nodes"],
                    "gap_after_step": r0["gap"], "incumbent": r0["obj"],
                    "certified_optimal": r0["status"] == 0, "solve_seconds": r0["seconds"],

@@ -244,8 +244,8 @@ typedef struct {
                            least node_sr samples may get a sample set of its
                            own, kept by its whole subtree, when that deletes
                            at least a quarter of them. Tries are budgeted by
-                           counted work, so runs repeat exactly; 65536 suits
-                           10^6..10^9 samples; 0 = off                      */
+                           counted work; 65536 suits 10^6..10^9 samples;
+                           0 = off                                          */
   int32_t reserved1;
   int64_t fft_start;    /* first FFT sample                                 */
   int64_t max_nodes;    /* 0 = unlimited                                    */

@@ -1193,8 +1193,7 @@ struct Solver {
       // quarter of the previous pass's evaluations, and a node is tried only
       // while at least a quarter of the recent tries at its lb / alpha (in
       // tenths) were kept. One try every 16 passes goes ahead regardless, so
-      // the rates can recover. Every rule counts work, not time, so runs
-      // repeat exactly.
+      // the rates can recover. These rules count work, not time.
       ++n_pass;
       if (o.node_sr > 0) {
         const double tn = now_s();
