@@ -44,7 +44,8 @@ WORKLOADS = {
     # 5 attributes): solve to the certified optimum with per-node carry-over,
     # capped at 120 s
     "mixture_50m_d5_k4": dict(n=50_000_000, d=5, k=4, std=0.1, outliers=0.0, seed=10001,
-                              batch=64, i_sr=2, passes=None, node_sr=65536, time_limit=120.0),
+                              batch=64, i_sr=2, passes=None, node_sr=65536, time_limit=120.0,
+                              learned=True),
     # a step is one lower-bound pass of one node (K boxes) over all samples:
     # the per-node bound evaluation itself, bound by HBM bandwidth
     "lb_1b_d2_k3": dict(n=1_000_000_000, d=2, k=3, std=0.05, outliers=0.0, seed=0,
@@ -242,6 +243,16 @@ def main() -> int:
     dom = max(kernels, key=lambda k: kernels[k]["seconds"])
     r0 = runs[0]
 
+    # untimed: the same solve with the committed branching network (the
+    # steps above use the max-range rule)
+    learned = None
+    if W.get("learned"):
+        from paper_2301_00061_amd import learn
+        wb, _ = learn.load()
+        rl = api.solve(x, n, k, branching=1, mlp_w=wb, **opts)
+        learned = {"solve_seconds": rl["seconds"], "nodes": rl["nodes"],
+                   "certified_optimal": rl["status"] == 0, "incumbent": rl["obj"], "gap": rl["gap"]}
+
     # untimed: best objective of Algorithm 2 from 100 starts, the heuristic
     # the certified incumbent is compared with
     import numpy as np
@@ -275,7 +286,7 @@ def main() -> int:
                    "gap_after_step": r0["gap"], "incumbent": r0["obj"],
                    "certified_optimal": r0["status"] == 0, "solve_seconds": r0["seconds"],
                    "fft100_best_obj": fft100, "ub_reduction_vs_fft100": (fft100 - r0["obj"]) / fft100,
-                   "lb_kernel_ms_per_step": lb_s * 1e3},
+                   "lb_kernel_ms_per_step": lb_s * 1e3, "learned_rule": learned},
         "roofline": {"bound": "alu", "kernel": dom, "achieved": kernels[dom]["achieved"],
                      "peak": VALU_PEAK_TOPS, "unit": "Tlane-op/s", "frac": kernels[dom]["frac"],
                      "traffic": profiled_traffic(dom, args.workload),
