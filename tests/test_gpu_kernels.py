@@ -194,8 +194,19 @@ def _tighten_case(seed, n, d, k, nn=1, with_refs=True, alpha_scale=1.2, ordered=
     hi = np.concatenate(his).astype(np.float32)
     off = (np.arange(nn + 1) * k).astype(np.int32)
     if with_refs:
-        ref_off = np.arange(nn * k + 1, dtype=np.int32)
-        ref = np.tile(X[T], (nn, 1)).astype(np.float32)
+        # with_refs refs per box: the FFT center, or random samples among the
+        # 20 r nearest to it, in random order
+        r = int(with_refs)
+        ref_off = (np.arange(nn * k + 1) * r).astype(np.int32)
+        rows = []
+        for m in range(nn):
+            for j in range(k):
+                if r == 1:
+                    rows.append(X[T[j]][None])
+                    continue
+                near = np.argsort(((X64 - X64[T[j]]) ** 2).sum(1), kind="stable")[:20 * r]
+                rows.append(X[rng.choice(near, r, replace=False)])
+        ref = np.concatenate(rows).astype(np.float32)
     else:
         ref_off, ref = None, None
     return X, off, lo, hi, alpha, ref_off, ref
@@ -209,7 +220,12 @@ def _tighten_case(seed, n, d, k, nn=1, with_refs=True, alpha_scale=1.2, ordered=
     # Morton-ordered samples: the wavefront bounding-box decisions take over
     (10, 40000, 2, 3, 1, True, True, 1.2), (11, 30001, 3, 5, 4, True, True, 0.6),
     (12, 20000, 4, 5, 6, False, True, 1.2), (13, 7777, 2, 3, 2, True, True, 0.3),
-    (14, 50000, 5, 4, 3, True, True, 2.0)])
+    (14, 50000, 5, 4, 3, True, True, 2.0),
+    # several refs per box (up to the 50 of Section 4.1.2): the refs' bounding
+    # box, the extremes-first order and the per-ref scans
+    (20, 20000, 2, 3, 1, 7, False, 0.4), (21, 30000, 3, 4, 3, 50, False, 0.5),
+    (22, 20000, 5, 4, 2, 12, True, 0.6), (23, 9000, 2, 3, 4, 33, True, 0.5),
+    (24, 12000, 4, 5, 1, 20, False, 0.35)])
 def test_tighten_parity(kc, seed, n, d, k, nn, with_refs, ordered, ascale):
     X, off, lo, hi, alpha, ref_off, ref = _tighten_case(seed, n, d, k, nn, with_refs, ascale, ordered)
     X64 = X.astype(np.float64)
@@ -218,7 +234,7 @@ def test_tighten_parity(kc, seed, n, d, k, nn, with_refs, ordered, ascale):
     xd = kc.to_device_soa(X)
     dev = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a)).cuda()
     out = kc.tighten(xd, n, dev(off), dev(lo), dev(hi), alpha, dev(ref_off), dev(ref),
-                     labels=(nn == 1), k_max=k, max_refs=1 if with_refs else None)
+                     labels=(nn == 1), k_max=k, max_refs=int(with_refs) if with_refs else None)
     res = {key: (v.cpu().numpy() if v is not None else None) for key, v in out.items()}
     unstable_nodes = 0
     for m in range(nn):
@@ -262,23 +278,35 @@ def test_tighten_parity(kc, seed, n, d, k, nn, with_refs, ordered, ascale):
     assert unstable_nodes <= max(1, nn // 3)
 
 
-@pytest.mark.parametrize("seed,n,d,nn,k", [(0, 10000, 2, 5, 3), (1, 50021, 3, 20, 5),
-                                           (2, 3000, 4, 1, 4), (3, 1025, 2, 3, 2),
-                                           (4, 8000, 12, 4, 3)])
-def test_reduce_parity(kc, seed, n, d, nn, k):
+@pytest.mark.parametrize("seed,n,d,nn,k,nref", [(0, 10000, 2, 5, 3, 1), (1, 50021, 3, 20, 5, 1),
+                                                (2, 3000, 4, 1, 4, 1), (3, 1025, 2, 3, 2, 1),
+                                                (4, 8000, 12, 4, 3, 1),
+                                                # several refs per box (UB-redundancy scans)
+                                                (5, 20000, 2, 4, 3, 9), (6, 12000, 3, 2, 4, 50)])
+def test_reduce_parity(kc, seed, n, d, nn, k, nref):
     X = datagen.gaussian_mixture(n, d, 3, 0.1, seed)
     X64 = X.astype(np.float64)
     off, lo, hi = datagen.random_boxes(nn, k, d, seed, wmin=0.05, wmax=0.6)
     rng = np.random.default_rng(seed)
     nb = lo.shape[0]
-    ref_off = np.arange(nb + 1, dtype=np.int32)
-    ref = X[rng.integers(0, n, nb)].astype(np.float32)
+    ref_off = (np.arange(nb + 1) * nref).astype(np.int32)
+    if nref == 1:
+        ref = X[rng.integers(0, n, nb)].astype(np.float32)
+    else:
+        # refs among the samples nearest each box's center, so that deciding
+        # UB-redundancy takes more than the first ref for many samples
+        rows = []
+        for b in range(nb):
+            c = 0.5 * (lo[b].astype(np.float64) + hi[b])
+            near = np.argsort(((X64 - c) ** 2).sum(1), kind="stable")[:5 * nref]
+            rows.append(X[rng.choice(near, nref, replace=False)])
+        ref = np.concatenate(rows).astype(np.float32)
     # beta at the median over samples of the worst node's farthest-corner
     # distance, so that about half of the samples are deletable
     far = np.stack([np.maximum(np.abs(X64[:, None, :] - lo[off[m]:off[m + 1]][None]),
                                np.abs(X64[:, None, :] - hi[off[m]:off[m + 1]][None])) ** 2
                     for m in range(nn)], 0).sum(-1).min(-1).max(0)
-    beta, alpha = float(np.quantile(far, 0.5)), 0.01
+    beta, alpha = float(np.quantile(far, 0.5)), (0.01 if nref == 1 else 0.03)
     g, eta = _g(kc, d)
     delta = 3 * g + 1e-12
     args = (off, lo.astype(np.float64), hi.astype(np.float64), ref_off, ref.astype(np.float64))
@@ -289,7 +317,7 @@ def test_reduce_parity(kc, seed, n, d, nn, k):
     idx_in = dev((np.arange(n, dtype=np.uint32) * 7 + 3).view(np.int32))
     x_out, idx_out, n_out, keep_g = kc.reduce(xd, n, dev(off), dev(lo), dev(hi), beta, alpha,
                                               dev(ref_off), dev(ref), idx_in=idx_in,
-                                              want_keep=True)
+                                              want_keep=True, max_refs=nref)
     keep_g = keep_g.cpu().numpy()
     stable = keep_o == keep_lo
     assert np.array_equal(keep_g[stable], keep_o[stable])
