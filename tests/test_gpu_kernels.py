@@ -48,6 +48,9 @@ LB_CASES = [
     (1500, 16, 2, 3, False, 7),
     (777, 2, 3, 40, True, 8),
     (70000, 3, 256, 10, False, 9),
+    # the most boxes per node (64), also with the most attributes (16)
+    (3000, 2, 3, 64, False, 15),
+    (1100, 16, 2, 64, True, 16),
 ]
 # Morton-ordered samples (the wavefront bounding-box skips take over)
 LB_ORDERED = [(60000, 2, 9, 3, False, 10), (50021, 3, 17, 5, True, 11),
@@ -136,7 +139,8 @@ def test_lower_bound_is_deterministic(kc):
 @pytest.mark.parametrize("n,d,ns,k,seed,ordered", [
     (1, 2, 1, 1, 0, False), (4097, 2, 3, 3, 1, False), (30011, 4, 9, 5, 2, False),
     (10000, 5, 40, 8, 3, False), (2000, 11, 2, 4, 4, False),
-    (60000, 2, 5, 3, 5, True), (40000, 4, 9, 5, 6, True)])
+    (60000, 2, 5, 3, 5, True), (40000, 4, 9, 5, 6, True),
+    (5000, 3, 6, 64, 7, False), (1500, 16, 3, 64, 8, False)])
 def test_objective_parity(kc, n, d, ns, k, seed, ordered):
     X = datagen.gaussian_mixture(n, d, 3, 0.1, seed)
     if ordered:
@@ -225,7 +229,9 @@ def _tighten_case(seed, n, d, k, nn=1, with_refs=True, alpha_scale=1.2, ordered=
     # box, the extremes-first order and the per-ref scans
     (20, 20000, 2, 3, 1, 7, False, 0.4), (21, 30000, 3, 4, 3, 50, False, 0.5),
     (22, 20000, 5, 4, 2, 12, True, 0.6), (23, 9000, 2, 3, 4, 33, True, 0.5),
-    (24, 12000, 4, 5, 1, 20, False, 0.35)])
+    (24, 12000, 4, 5, 1, 20, False, 0.35),
+    # the most boxes per node (64; several chunks of boxes per workgroup)
+    (25, 6000, 2, 64, 2, False, False, 1.2), (26, 4000, 3, 64, 1, 3, False, 0.6)])
 def test_tighten_parity(kc, seed, n, d, k, nn, with_refs, ordered, ascale):
     X, off, lo, hi, alpha, ref_off, ref = _tighten_case(seed, n, d, k, nn, with_refs, ascale, ordered)
     X64 = X.astype(np.float64)
