@@ -515,3 +515,50 @@ def test_autotuned_candidate_variant_matches_default(kc, n, d, nn, k, seed):
     after = kc.lower_bound(xd, n, *args, want_cand=True, h=h)
     for a, b in zip(before, after):
         assert torch.equal(a, b)
+
+
+def test_abi_rejects_malformed_requests(kc):
+    """The C ABI's host-side checks: every malformed request returns KC_EINVAL
+    with a message before anything is launched (empty or oversized sample
+    sets, bad leading dimension or alignment, attribute counts outside 1..16,
+    empty node batches, box counts outside 1..64, missing pointers)."""
+    import ctypes as C
+    from paper_2301_00061_amd import _lib
+    h = kc.handle()
+    L, hp = h.lib, h.ptr
+    x = torch.zeros((2, 64), dtype=torch.float32, device="cuda")
+    off = torch.tensor([0, 1], dtype=torch.int32, device="cuda")
+    lo = torch.zeros((1, 2), dtype=torch.float32, device="cuda")
+    hi = torch.ones((1, 2), dtype=torch.float32, device="cuda")
+    out = torch.empty(8, dtype=torch.float64, device="cuda")
+    good_p = dict(x=x.data_ptr(), n=10, ld=64, d=2, reserved=0)
+    good_m = dict(n_nodes=1, n_boxes=1, k_max=1, reserved=0, box_off=off.data_ptr(),
+                  lo=lo.data_ptr(), hi=hi.data_ptr())
+    o = C.c_void_p(out.data_ptr())
+
+    def lb(p, m, outp=o):
+        P, M = _lib.Points(**{**good_p, **p}), _lib.Nodes(**{**good_m, **m})
+        return L.kc_lower_bound(hp, C.byref(P), C.byref(M), None, outp, None, None, None)
+
+    def rejected(rc):
+        return rc == -1 and len(L.kc_last_error(hp) or b"") > 0
+
+    for p in (dict(x=None), dict(n=0), dict(n=1 << 31, ld=1 << 31), dict(ld=8), dict(ld=66),
+              dict(d=0), dict(d=17), dict(x=x.data_ptr() + 4)):
+        assert rejected(lb(p, {})), p
+    for m in (dict(n_nodes=0), dict(n_boxes=-1), dict(k_max=0), dict(k_max=65),
+              dict(box_off=None), dict(lo=None)):
+        assert rejected(lb({}, m)), m
+    assert rejected(lb({}, {}, outp=None))  # no output requested
+    P = _lib.Points(**good_p)
+    cen = C.c_void_p(lo.data_ptr())
+    for ns, k, prec in ((0, 1, 64), (1, 0, 64), (1, 65, 64), (1, 1, 16)):
+        rc = L.kc_objective(hp, C.byref(P), ns, k, cen, prec, o, None, None)
+        assert rejected(rc), (ns, k, prec)
+    M = _lib.Nodes(**good_m)
+    for r in (dict(ref_off=None), dict(n_refs=-1), dict(max_per_box=65), dict(ref=None)):
+        R = _lib.Refs(**{**dict(n_refs=1, max_per_box=1, ref_off=off.data_ptr(),
+                                 ref=lo.data_ptr()), **r})
+        rc = L.kc_tighten(hp, C.byref(P), C.byref(M), 1.0, C.byref(R), o, o, o, o, o, o, o, None,
+                          None, None)
+        assert rejected(rc), r
