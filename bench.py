@@ -184,9 +184,8 @@ def main() -> int:
                          "(0 = off; default: the workload's setting)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; the sample-sharded multi-GPU path is a "
-              "design (see the sharding section of the design notes), not part of the build.",
-              file=sys.stderr)
+        print("bench.py: the library runs on one GPU; sharding the samples over several GPUs "
+              "is described in the design notes but not implemented.", file=sys.stderr)
         return 2
 
     import torch
