@@ -214,6 +214,7 @@ struct Solver {
   double t_tighten = 0, t_reduce = 0, t_branch = 0, t_bound = 0;
   double last_pass_s = 0;  // wall time of the previous pass without its reduction
   int64_t sr_interval = 0, sr_runs = 0;
+  int64_t n_bounded = 0, n_bounded_pruned = 0;  // bounded nodes, and those the bound prunes
   // subtree sample sets: bytes held and the cap on them; measured cost of a
   // one-node reduction per sample of the node
   size_t set_bytes = 0, set_cap = 0;  // held by live and pooled sets
@@ -1298,8 +1299,9 @@ struct Solver {
     if (o.verbose)
       fprintf(stderr,
               "[kc_solve] phases: tighten %.3fs reduce %.3fs (%lld runs) branch %.3fs bound %.3fs "
-              "total %.3fs\n",
-              t_tighten, t_reduce, (long long)sr_runs, t_branch, t_bound, now_s() - t0);
+              "total %.3fs; bounded %lld nodes, %lld pruned by their bound\n",
+              t_tighten, t_reduce, (long long)sr_runs, t_branch, t_bound, now_s() - t0,
+              (long long)n_bounded, (long long)n_bounded_pruned);
     return KC_OK;
   }
 
@@ -1410,6 +1412,10 @@ struct Solver {
     }
     const double thr = prune_thr();
     const double rel = kc_rel_margin(D) + 0x1p-50, eta = kc_abs_margin(D);
+    for (int i = 0; i < ne; ++i) {
+      ++n_bounded;
+      if (!is_leaf[i] && std::max(ev[i]->lb, lb[i]) >= thr) ++n_bounded_pruned;
+    }
     for (int i = 0; i < ne; ++i) {
       Node *m = ev[i];
       if (!ok[i]) {
