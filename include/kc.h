@@ -263,8 +263,21 @@ typedef struct {
   int32_t sb_every;     /* 0 = no labels                                    */
   int32_t sb_cap;
   float *sb_feat;       /* host [sb_cap][32] candidate features             */
-  float *sb_score;      /* host [sb_cap] product score of the two children  */
+  float *sb_score;      /* host [sb_cap] product score of the two children:
+                           max(dL, e) max(dR, e) / alpha^2, d = child lower
+                           bound (alpha for a child with an empty box, at most
+                           alpha) minus the node's, e = 1e-6 alpha          */
   int32_t *sb_node;     /* host [sb_cap] ordinal of the labelled node       */
+  /* Optional (nullable) host arrays describing each row, so that a score can
+   * be recomputed from its definition: the labelled node's tightened boxes
+   * (sb_lo, sb_hi: [sb_cap][k*d]), the candidate's (cluster, attribute)
+   * (sb_ka: [sb_cap][2]; split as in branching, [lo, m] and [next(m), hi]
+   * with m the float32 midpoint rounded down), and the node's lower bound and
+   * the incumbent alpha the score was formed with (sb_bounds: [sb_cap][2]). */
+  float *sb_lo;
+  float *sb_hi;
+  int32_t *sb_ka;
+  double *sb_bounds;
 } kc_opts;
 
 typedef struct {
@@ -282,7 +295,10 @@ typedef struct {
   double tighten_kernel_ms; /* total time inside kc_tighten launches        */
   int64_t tighten_evals;    /* sample-box evaluations of the tightening passes */
   int32_t seeds_found;
-  int32_t status;       /* 0 closed (gap <= eps_rel), 1 node limit, 2 time limit */
+  int32_t status;       /* 0 closed (gap <= eps_rel), 1 node limit, 2 time limit,
+                           3 no open node left but gap > eps_rel (only when
+                           eps_rel is below the float32 margins of the leaves
+                           and nodes that closed the search)               */
   int32_t sb_rows;      /* strong-branching rows written                     */
   int32_t sb_nodes;     /* strong-branching nodes labelled                   */
   int64_t node_sr_tries;/* one-node sample reductions run                    */

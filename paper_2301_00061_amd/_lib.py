@@ -45,7 +45,9 @@ class Opts(C.Structure):
                 ("reserved1", C.c_int32), ("fft_start", C.c_int64), ("max_nodes", C.c_int64), ("eps_rel", C.c_double),
                 ("time_limit_s", C.c_double), ("mlp_w", C.c_void_p), ("verbose", C.c_int32),
                 ("sb_first", C.c_int32), ("sb_every", C.c_int32), ("sb_cap", C.c_int32),
-                ("sb_feat", C.c_void_p), ("sb_score", C.c_void_p), ("sb_node", C.c_void_p)]
+                ("sb_feat", C.c_void_p), ("sb_score", C.c_void_p), ("sb_node", C.c_void_p),
+                ("sb_lo", C.c_void_p), ("sb_hi", C.c_void_p), ("sb_ka", C.c_void_p),
+                ("sb_bounds", C.c_void_p)]
 
 
 class Result(C.Structure):

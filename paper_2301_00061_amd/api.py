@@ -253,6 +253,11 @@ def solve(x, n, k, batch=64, i_sr=4, use_bt=True, use_seeds=True, max_refs=50, b
         o.sb_feat = sb.feat.ctypes.data
         o.sb_score = sb.score.ctypes.data
         o.sb_node = sb.node.ctypes.data
+        if sb.lo is not None:
+            o.sb_lo = sb.lo.ctypes.data
+            o.sb_hi = sb.hi.ctypes.data
+            o.sb_ka = sb.ka.ctypes.data
+            o.sb_bounds = sb.bounds.ctypes.data
     r = Result()
     torch.cuda.synchronize()
     h.check(h.lib.kc_solve(h.ptr, C.byref(P), C.byref(o), C.byref(r)), "kc_solve")
@@ -268,11 +273,18 @@ class StrongBranchingBuffer:
     """Host arrays kc_solve fills with strong-branching rows (features,
     product score, labelled-node ordinal)."""
 
-    def __init__(self, cap: int, first: int = 32, every: int = 8):
+    def __init__(self, cap: int, first: int = 32, every: int = 8, kd: int | None = None):
         self.cap, self.first, self.every = int(cap), int(first), int(every)
         self.feat = np.zeros((self.cap, 32), dtype=np.float32)
         self.score = np.zeros(self.cap, dtype=np.float32)
         self.node = np.zeros(self.cap, dtype=np.int32)
+        # with kd = K*D: each row's node boxes, candidate (k, a), node LB and alpha
+        self.lo = self.hi = self.ka = self.bounds = None
+        if kd is not None:
+            self.lo = np.zeros((self.cap, kd), dtype=np.float32)
+            self.hi = np.zeros((self.cap, kd), dtype=np.float32)
+            self.ka = np.zeros((self.cap, 2), dtype=np.int32)
+            self.bounds = np.zeros((self.cap, 2), dtype=np.float64)
 
 
 def rel_margin(d: int) -> float:

@@ -67,7 +67,8 @@ kc_status kc_spatial_order(kc_handle *h, const kc_points *in, const uint32_t *id
   A.n = n;
   A.ld = in->ld;
   A.d = d;
-  A.bits = 32 / d;
+  // at most 31 bits per attribute, so that 1u << bits stays defined (d = 1)
+  A.bits = 32 / d < 31 ? 32 / d : 31;
   const float qmax = (float)((1u << A.bits) - 1u);
   for (int a = 0; a < d; ++a) {
     A.lo[a] = lo[a];

@@ -1080,6 +1080,18 @@ struct Solver {
                &o.sb_feat[(size_t)sb_rows * NFEAT]);
       o.sb_score[sb_rows] = (float)(g[0] * g[1] / (al * al));
       o.sb_node[sb_rows] = sb_nodes - 1;
+      if (o.sb_lo && o.sb_hi) {
+        std::memcpy(o.sb_lo + (size_t)sb_rows * K * D, m->lo.data(), (size_t)K * D * 4);
+        std::memcpy(o.sb_hi + (size_t)sb_rows * K * D, m->hi.data(), (size_t)K * D * 4);
+      }
+      if (o.sb_ka) {
+        o.sb_ka[2 * sb_rows] = cands[c].k;
+        o.sb_ka[2 * sb_rows + 1] = cands[c].a;
+      }
+      if (o.sb_bounds) {
+        o.sb_bounds[2 * sb_rows] = m->lb;
+        o.sb_bounds[2 * sb_rows + 1] = al;
+      }
       ++sb_rows;
     }
     return KC_OK;
@@ -1337,7 +1349,7 @@ struct Solver {
     const size_t o_lb = out.take((size_t)ne * 8), o_ids = out.take(ng * 8),
                  o_xy = out.take(ng * D * 4), o_orig = out.take(ng * 8),
                  o_obj = out.take((size_t)ne * 8), o_oam = out.take((size_t)ne * 8),
-                 o_cert = out.take(8), o_cam = out.take(8);
+                 o_cert = out.take(8), o_cam = out.take(8), o_l64 = out.take((size_t)ne * 8);
     kc_status s = reserve();
     if (s) return s;
     for (size_t g = 0; g < R.size(); ++g) fill_boxes(plans[g], glo[g], ghi[g], nullptr);
@@ -1416,6 +1428,35 @@ struct Solver {
       ++n_bounded;
       if (!is_leaf[i] && std::max(ev[i]->lb, lb[i]) >= thr) ++n_bounded_pruned;
     }
+    // A leaf's only solution is its single-point centers. The float32 screen
+    // bounds their objective from below by ub (1 - 2 gamma) only, which at
+    // many attributes lies more than eps_rel below the incumbent when the leaf
+    // ties it; such leaves get their objective in float64 (over the leaf's
+    // samples, which give the objective over all samples), so that the final
+    // gap closes.
+    std::vector<double> leaf64(ne, -1.0);
+    {
+      std::vector<int> band;
+      for (int i = 0; i < ne; ++i) {
+        if (!is_leaf[i] || !ok[i]) continue;
+        const double lo_obj = std::max(0.0, (ub[i] - eta) / (1.0 + rel) * (1.0 - rel) - eta);
+        if (std::max(ev[i]->lb, lo_obj) < alpha_cert * (1.0 - o.eps_rel)) band.push_back(i);
+      }
+      if (!band.empty()) {
+        double *d64 = out.dp<double>(o_l64), *h64 = out.hp<double>(o_l64);
+        for (const int i : band) {
+          const kc_points p = pts_of(ev[i]);
+          if ((s = kc_objective(h, &p, 1, K, out.dp<float>(o_xy) + (size_t)i * K * D, 64, d64 + i,
+                                nullptr, st)))
+            return s;
+          res->passes++;
+        }
+        if (hipMemcpyAsync(h64, d64, (size_t)ne * 8, hipMemcpyDeviceToHost, st) != hipSuccess)
+          return kc_fail(h, KC_EDEVICE, "download");
+        if ((s = sync("leaf certificate"))) return s;
+        for (const int i : band) leaf64[i] = h64[i];
+      }
+    }
     for (int i = 0; i < ne; ++i) {
       Node *m = ev[i];
       if (!ok[i]) {
@@ -1431,7 +1472,9 @@ struct Solver {
       }
       if (is_leaf[i]) {
         // every box is one point: the node's only solution has objective ub[i]
-        const double lo_obj = std::max(0.0, (ub[i] - eta) / (1.0 + rel) * (1.0 - rel) - eta);
+        // (float32, rounded up), or leaf64[i] (float64, within (D+3) 2^-53)
+        double lo_obj = std::max(0.0, (ub[i] - eta) / (1.0 + rel) * (1.0 - rel) - eta);
+        if (leaf64[i] >= 0.0) lo_obj = std::max(lo_obj, leaf64[i] * (1.0 - (D + 3) * 0x1p-52));
         lb_closed = std::min(lb_closed, std::max(m->lb, lo_obj));
         delete m;
       } else if (m->lb >= thr) {
@@ -1476,6 +1519,8 @@ extern "C" kc_status kc_solve(kc_handle *h, const kc_points *pts, const kc_opts 
     res->obj = S.alpha_cert;
     res->lb = S.global_lb();
     res->gap = S.alpha_cert > 0 ? (S.alpha_cert - res->lb) / S.alpha_cert : 0.0;
+    // the open set ran out, but the certified gap is above eps_rel
+    if (res->status == 0 && res->gap > opts->eps_rel) res->status = 3;
     for (int k = 0; k < opts->k; ++k) res->centers[k] = S.inc_ids[k];
     res->n_active = S.act.n;
     res->sb_rows = S.sb_rows;

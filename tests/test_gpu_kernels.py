@@ -233,36 +233,53 @@ def _tighten_case(seed, n, d, k, nn=1, with_refs=True, alpha_scale=1.2, ordered=
     # the most boxes per node (64; several chunks of boxes per workgroup)
     (25, 6000, 2, 64, 2, False, False, 1.2), (26, 4000, 3, 64, 1, 3, False, 0.6)])
 def test_tighten_parity(kc, seed, n, d, k, nn, with_refs, ordered, ascale):
-    X, off, lo, hi, alpha, ref_off, ref = _tighten_case(seed, n, d, k, nn, with_refs, ascale, ordered)
+    X, off, lo, hi, alpha0, ref_off, ref = _tighten_case(seed, n, d, k, nn, with_refs, ascale, ordered)
     X64 = X.astype(np.float64)
     g, eta = _g(kc, d)
     delta = 3 * g + 1e-12
+
+    def oracle_runs(alpha):
+        """Oracle tightening of every node at alpha and at the two ends of
+        the margin band around it."""
+        per_node = []
+        for m in range(nn):
+            sl = slice(off[m], off[m + 1])
+            r_off = None if ref_off is None else (ref_off[off[m]:off[m + 1] + 1] - ref_off[off[m]])
+            r = None if ref is None else ref[ref_off[off[m]]:ref_off[off[m + 1]]].astype(np.float64)
+            per_node.append([oracle.tighten_node(X64, lo[sl].astype(np.float64),
+                                                 hi[sl].astype(np.float64), a, r_off, r,
+                                                 want_labels=True)
+                             for a in (alpha, alpha * (1 - delta), alpha * (1 + delta))])
+        return per_node
+
+    def stable(runs):
+        o = runs[0]
+        return all(np.array_equal(rr["labels"], o["labels"]) and rr["n_excluded"] == o["n_excluded"]
+                   and all(np.array_equal(rr[key], o[key])
+                           for key in ("bb_lo", "bb_hi", "n_in", "asg_min", "asg_max", "n_asg"))
+                   for rr in runs[1:])
+
+    # alpha moved by small steps until no sample of any node lies in the
+    # margin band of any test (the device may decide either way there), so
+    # that every node is compared element by element
+    for t in range(24):
+        alpha = alpha0 * (1.0 + 1.3e-3 * t)
+        per_node = oracle_runs(alpha)
+        if all(stable(runs) for runs in per_node):
+            break
+    else:
+        pytest.fail("no alpha near the case's value keeps every node out of the margin band")
+
     xd = kc.to_device_soa(X)
     dev = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a)).cuda()
     out = kc.tighten(xd, n, dev(off), dev(lo), dev(hi), alpha, dev(ref_off), dev(ref),
                      labels=(nn == 1), k_max=k, max_refs=int(with_refs) if with_refs else None)
     res = {key: (v.cpu().numpy() if v is not None else None) for key, v in out.items()}
-    unstable_nodes = 0
     for m in range(nn):
         sl = slice(off[m], off[m + 1])
-        r_off = None if ref_off is None else (ref_off[off[m]:off[m + 1] + 1] - ref_off[off[m]])
-        r = None if ref is None else ref[ref_off[off[m]]:ref_off[off[m + 1]]].astype(np.float64)
-        runs = [oracle.tighten_node(X64, lo[sl].astype(np.float64), hi[sl].astype(np.float64),
-                                    a, r_off, r, want_labels=True)
-                for a in (alpha, alpha * (1 - delta), alpha * (1 + delta))]
-        o = runs[0]
-        stable = np.ones(n, dtype=bool)
-        for rr in runs[1:]:
-            stable &= rr["labels"] == o["labels"]
+        o = per_node[m][0]
         if nn == 1:
-            lab = res["labels"]
-            assert np.array_equal(lab[stable], o["labels"][stable])
-            assert (~stable).sum() <= max(2, n // 1000)
-        same_aggs = all(np.array_equal(rr[key], o[key]) for rr in runs[1:]
-                        for key in ("bb_lo", "bb_hi", "n_in", "asg_min", "asg_max", "n_asg"))
-        if not (same_aggs and stable.all()):
-            unstable_nodes += 1
-            continue
+            assert np.array_equal(res["labels"], o["labels"])
         assert res["n_excl"][m] == o["n_excluded"]
         assert np.array_equal(res["n_in"][sl], o["n_in"])
         assert np.array_equal(res["n_asg"][sl], o["n_asg"])
@@ -281,7 +298,9 @@ def test_tighten_parity(kc, seed, n, d, k, nn, with_refs, ordered, ascale):
             mid = 0.5 * (lo[off[m] + j].astype(np.float64) + hi[off[m] + j])
             dist = lambda s_: ((X64[s_] - mid) ** 2).sum()
             assert dist(fg) >= dist(fo) * (1 - 4 * g) - 1e-6 * (1 + np.abs(mid).max())
-    assert unstable_nodes <= max(1, nn // 3)
+    # the cases exercise every aggregate: some box holds assigned samples
+    # and some box holds candidate centers
+    assert res["n_in"].sum() > 0 or n == 1
 
 
 @pytest.mark.parametrize("seed,n,d,nn,k,nref", [(0, 10000, 2, 5, 3, 1), (1, 50021, 3, 20, 5, 1),
@@ -347,16 +366,25 @@ def test_reduce_without_refs_and_identity_index(kc):
     lo = np.array([[0.2, 0.2], [0.5, 0.5], [0.8, 0.1]], dtype=np.float32)
     hi = lo + np.float32(0.05)
     beta = 0.02
-    keep_o = oracle.reduce_flags(X.astype(np.float64), off, lo.astype(np.float64),
-                                 hi.astype(np.float64), np.zeros(4, dtype=np.int32),
-                                 np.zeros((1, 2)), beta, 1.0)
+    g, eta = _g(kc, 2)
+    delta = 3 * g + 1e-12
+    args = (X.astype(np.float64), off, lo.astype(np.float64), hi.astype(np.float64),
+            np.zeros(4, dtype=np.int32), np.zeros((1, 2)))
+    keep_o = oracle.reduce_flags(*args, beta, 1.0)
+    keep_lo = oracle.reduce_flags(*args, beta * (1 - delta), 1.0)
     xd = kc.to_device_soa(X)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
     x_out, idx_out, n_out, keep_g = kc.reduce(xd, len(X), dev(off), dev(lo), dev(hi), beta, 1.0,
                                               want_keep=True)
     kg = keep_g.cpu().numpy()
-    diff = np.nonzero(kg != keep_o)[0]
-    assert len(diff) <= 2
+    # identical outside the margin band; inside it the device keeps the sample
+    # (it deletes a subset of the exact deletions and a superset of those at
+    # beta moved down by the margin)
+    stable = keep_o == keep_lo
+    assert np.array_equal(kg[stable], keep_o[stable])
+    assert np.all(kg >= keep_o) and np.all(kg <= keep_lo)
+    assert (~stable).sum() <= 2
+    assert 0 < keep_o.sum() < len(X)
     sel = np.nonzero(kg)[0]
     assert int(n_out.item()) == len(sel)
     assert np.array_equal(idx_out.cpu().numpy()[:len(sel)], sel)

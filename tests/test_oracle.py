@@ -435,3 +435,99 @@ def test_node_reduction_carries_over_to_descendants(orc, seed):
         assert np.array_equal(ta["bb_lo"][has], tk["bb_lo"][has])
         assert np.array_equal(ta["bb_hi"][has], tk["bb_hi"][has])
     assert checked > 0
+
+
+def _hand_reduce_candidates():
+    with open(os.path.join(os.path.dirname(__file__), "golden", "reduce_and_candidates_hand.json")) as f:
+        return json.load(f)
+
+
+def test_candidates_hand_worked(orc):
+    """Section 3.2 on a hand-worked fixture: a nearer sample outside the box is
+    not a candidate, exact ties go to the lowest index, point boxes and empty
+    boxes."""
+    c = _hand_reduce_candidates()["candidates"]
+    X = np.array(c["points"], dtype=np.float64)
+    cand = orc.candidates(X, np.array(c["lo"]), np.array(c["hi"]))
+    assert cand.tolist() == c["cand"]
+
+
+def _reduce_case(node_list):
+    lo = np.concatenate([np.array(n["lo"]) for n in node_list])
+    hi = np.concatenate([np.array(n["hi"]) for n in node_list])
+    off = np.arange(0, 2 * len(node_list) + 1, 2, dtype=np.int32)
+    rows, roff = [], [0]
+    for n in node_list:
+        for refs in n["refs"]:
+            rows.extend(refs)
+            roff.append(len(rows))
+    return off, lo, hi, np.array(roff, dtype=np.int32), np.array(rows, dtype=np.float64)
+
+
+def test_reduction_flags_hand_worked(orc):
+    """Algorithm 5 on a hand-worked 1-D fixture: one far ref of a box suffices
+    for UB-redundancy, the LB test is strict, and a sample is deleted only when
+    redundant in every node."""
+    r = _hand_reduce_candidates()["reduce"]
+    X = np.array(r["points"], dtype=np.float64)
+    for nodes, want in (([r["node1"]], r["keep_node1"]), ([r["node1"], r["node2"]], r["keep_both"])):
+        keep = orc.reduce_flags(X, *_reduce_case(nodes), r["beta"], r["alpha"])
+        assert keep.tolist() == want
+
+
+def _far_corner(x, lo, hi):
+    corners = np.array(list(itertools.product(*[(lo[a], hi[a]) for a in range(len(x))])))
+    return ((corners - x) ** 2).sum(1).max()
+
+
+def _redundant_everywhere(x, off, lo, hi, ref_off, ref, beta, alpha, every_ref=False):
+    """Section 4.2 by brute force: corner enumeration for the farthest point of
+    each box, plain distances to every ref. every_ref=True plants a mistake
+    (all refs of a box must be far instead of one)."""
+    for m in range(len(off) - 1):
+        far, ub_red = [], True
+        for b in range(off[m], off[m + 1]):
+            far.append(_far_corner(x, lo[b], hi[b]))
+            inside = np.all((lo[b] <= x) & (x <= hi[b]))
+            dist = ((ref[ref_off[b]:ref_off[b + 1]] - x) ** 2).sum(1)
+            far_ok = np.all(dist > alpha) if every_ref else np.any(dist > alpha)
+            if inside and not far_ok:
+                ub_red = False
+        if not (min(far) < beta and ub_red):
+            return False
+    return True
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_reduction_flags_complete(orc, seed):
+    """Deleted exactly when redundant: every sample the oracle keeps fails the
+    LB or UB test in some node and every sample it deletes passes both in all
+    nodes (brute force over corners and refs), with several refs per box so
+    that some but not all refs of a box are far."""
+    X = datagen.gaussian_mixture(300, 2, 3, 0.08, 700 + seed).astype(np.float64)
+    off, lo, hi = datagen.random_boxes(3, 3, 2, 40 + seed, wmin=0.1, wmax=0.6)
+    lo, hi = lo.astype(np.float64), hi.astype(np.float64)
+    rng = np.random.default_rng(seed)
+    nb = lo.shape[0]
+    # per box: the sample nearest its midpoint (near the box's samples), then
+    # one to three random samples (mostly far from them)
+    counts = rng.integers(2, 5, nb)
+    ref_off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
+    rows = []
+    for b in range(nb):
+        mid = 0.5 * (lo[b] + hi[b])
+        rows.append(X[np.argmin(((X - mid) ** 2).sum(1))][None])
+        rows.append(X[rng.choice(len(X), counts[b] - 1, replace=False)])
+    ref = np.concatenate(rows)
+    # beta where about half of the samples pass the LB test in every node
+    worst = np.array([max(min(_far_corner(x, lo[b], hi[b]) for b in range(off[m], off[m + 1]))
+                          for m in range(len(off) - 1)) for x in X])
+    beta, alpha = float(np.quantile(worst, 0.5)), 0.01
+    keep = orc.reduce_flags(X, off, lo, hi, ref_off, ref, beta, alpha)
+    want = np.array([not _redundant_everywhere(x, off, lo, hi, ref_off, ref, beta, alpha) for x in X])
+    assert 0 < want.sum() < len(X)
+    assert np.array_equal(keep.astype(bool), want)
+    # the instance tells one far ref from all refs far
+    planted = np.array([not _redundant_everywhere(x, off, lo, hi, ref_off, ref, beta, alpha, True)
+                        for x in X])
+    assert not np.array_equal(planted, want)
