@@ -128,6 +128,24 @@ kc_status kc_lower_bound(kc_handle *h, const kc_points *pts, const kc_nodes *nod
                          float *lb_raw, double *lb_safe, int64_t *argmax, int64_t *cand,
                          void *stream);
 
+/* kc_lower_bound for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, results, validation and stream semantics as kc_lower_bound
+ * (same kernels and tiles), but the per-split partial results live in a
+ * static device array of KC_NOALLOC_SCRATCH_BYTES per GPU, whose address the
+ * handle takes once per device in kc_create; the call makes no device or host
+ * allocation and never synchronises. The caller still owns every input and
+ * output buffer. A request whose partial results exceed the array (roughly
+ * 8 bytes x (n_nodes + n_boxes with cand) x splits; at most about 2^19
+ * node+box slots in total) fails with KC_EINVAL and a message naming the
+ * limit. Every call on one GPU shares that GPU's array: calls that overlap on
+ * one GPU (several streams or host threads) race and give unspecified
+ * results; calls ordered on one stream are safe. */
+#define KC_NOALLOC_SCRATCH_BYTES (4u << 20)
+kc_status kc_lower_bound_noalloc(kc_handle *h, const kc_points *pts, const kc_nodes *nodes,
+                                 float *lb_raw, double *lb_safe, int64_t *argmax, int64_t *cand,
+                                 void *stream);
+
 /* Eq (12): for every candidate set c of k centers (centers[(c*k + j)*d + a]),
  *     obj[c] = max_s min_j ||x_s - center_j||^2 ,  argmax[c] its lowest index.
  * precision 32: float32 evaluation, obj rounded UP by the margin (>= exact).

@@ -13,11 +13,12 @@ LIB_PATH = os.path.join(HERE, "libkc.so")
 
 KC_OK, KC_EINVAL, KC_ENOMEM, KC_EDEVICE, KC_EUNSUPPORTED = 0, -1, -2, -3, -4
 MLP_PARAMS = 10497
+NOALLOC_SCRATCH_BYTES = 4 << 20  # KC_NOALLOC_SCRATCH_BYTES
 
 # every entry point declared in include/kc.h
 EXPORTS = [
     "kc_create", "kc_destroy", "kc_last_error", "kc_rel_margin", "kc_abs_margin",
-    "kc_lower_bound", "kc_objective", "kc_fft", "kc_tighten", "kc_reduce", "kc_autotune",
+    "kc_lower_bound", "kc_lower_bound_noalloc", "kc_objective", "kc_fft", "kc_tighten", "kc_reduce", "kc_autotune",
     "kc_mlp_forward", "kc_mlp_backward", "kc_mlp_loss", "kc_mlp_adam", "kc_solve",
 ]
 
@@ -87,6 +88,8 @@ def load(path: str = LIB_PATH):
     L.kc_abs_margin.argtypes = [C.c_int]
     L.kc_lower_bound.restype = st
     L.kc_lower_bound.argtypes = [vp, P(Points), P(Nodes), vp, vp, vp, vp, vp]
+    L.kc_lower_bound_noalloc.restype = st
+    L.kc_lower_bound_noalloc.argtypes = [vp, P(Points), P(Nodes), vp, vp, vp, vp, vp]
     L.kc_objective.restype = st
     L.kc_objective.argtypes = [vp, P(Points), C.c_int32, C.c_int32, vp, C.c_int32, vp, vp, vp]
     L.kc_fft.restype = st

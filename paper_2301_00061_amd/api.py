@@ -97,19 +97,28 @@ def refs(ref_off: torch.Tensor | None, ref: torch.Tensor | None, max_per_box: in
     return Refs(int(n_refs), int(max_per_box), ref_off.data_ptr(), ref.data_ptr() if n_refs else 0)
 
 
-def lower_bound(x, n, box_off, lo, hi, k_max=None, want_cand=False, h: Handle | None = None):
-    """Section 3.1 lower bound per node; returns (lb_raw, lb_safe, argmax, cand|None)."""
+def lower_bound(x, n, box_off, lo, hi, k_max=None, want_cand=False, h: Handle | None = None,
+                out=None, noalloc: bool = False):
+    """Section 3.1 lower bound per node; returns (lb_raw, lb_safe, argmax, cand|None).
+
+    ``out`` (optional) is a tuple of preallocated output tensors in that order;
+    ``noalloc`` calls ``kc_lower_bound_noalloc`` (static device scratch)."""
     h = h or handle()
     P = points(x, n)
     M = nodes(box_off, lo, hi, k_max)
     dev = x.device
-    lb_raw = torch.empty(M.n_nodes, dtype=torch.float32, device=dev)
-    lb_safe = torch.empty(M.n_nodes, dtype=torch.float64, device=dev)
-    am = torch.empty(M.n_nodes, dtype=torch.int64, device=dev)
-    cand = torch.empty(max(1, M.n_boxes), dtype=torch.int64, device=dev) if want_cand else None
-    h.check(h.lib.kc_lower_bound(h.ptr, C.byref(P), C.byref(M), _ptr(lb_raw), _ptr(lb_safe),
-                                 _ptr(am), _ptr(cand), _stream()), "kc_lower_bound")
-    return lb_raw, lb_safe, am, (cand[:M.n_boxes] if want_cand else None)
+    if out is None:
+        lb_raw = torch.empty(M.n_nodes, dtype=torch.float32, device=dev)
+        lb_safe = torch.empty(M.n_nodes, dtype=torch.float64, device=dev)
+        am = torch.empty(M.n_nodes, dtype=torch.int64, device=dev)
+        cand = torch.empty(max(1, M.n_boxes), dtype=torch.int64, device=dev) if want_cand else None
+    else:
+        lb_raw, lb_safe, am, cand = out
+    fn = h.lib.kc_lower_bound_noalloc if noalloc else h.lib.kc_lower_bound
+    name = "kc_lower_bound_noalloc" if noalloc else "kc_lower_bound"
+    h.check(fn(h.ptr, C.byref(P), C.byref(M), _ptr(lb_raw), _ptr(lb_safe), _ptr(am), _ptr(cand),
+               _stream()), name)
+    return lb_raw, lb_safe, am, (cand[:M.n_boxes] if cand is not None else None)
 
 
 def objective(x, n, centers: torch.Tensor, precision: int = 32, h: Handle | None = None):

@@ -14,15 +14,10 @@
 
 kc_status kc_fail(kc_handle *h, kc_status st, const char *fmt, ...) {
   if (h) {
-    char buf[512];
     va_list ap;
     va_start(ap, fmt);
-    vsnprintf(buf, sizeof(buf), fmt, ap);
+    vsnprintf(h->err, sizeof(h->err), fmt, ap);
     va_end(ap);
-    try {
-      h->err = buf;
-    } catch (...) {  // no memory for the message: keep the status
-    }
   }
   return st;
 }
@@ -160,7 +155,11 @@ extern "C" kc_status kc_create(kc_handle **out, int device, const char *tune_cac
     if (h->lds_per_block > 65536) h->lds_per_block = 65536;
   }
   if (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess) {
-    delete h;
+    kc_destroy(h);
+    return KC_EDEVICE;
+  }
+  if (kc_noalloc_setup(h) != KC_OK) {
+    kc_destroy(h);
     return KC_EDEVICE;
   }
   if (tune_cache_path && *tune_cache_path) {
@@ -187,7 +186,7 @@ extern "C" void kc_destroy(kc_handle *h) {
   delete h;
 }
 
-extern "C" const char *kc_last_error(const kc_handle *h) { return h ? h->err.c_str() : "null handle"; }
+extern "C" const char *kc_last_error(const kc_handle *h) { return h ? h->err : "null handle"; }
 
 // ------------------------------------------------------------ autotune ---
 
@@ -200,12 +199,10 @@ static int bucket_log2(int64_t v) {
   return b;
 }
 
-std::string kc_tune_key(int d, bool with_cand, int n_nodes, int k_max, int64_t n) {
+void kc_tune_key(char *buf, size_t size, int d, bool with_cand, int n_nodes, int k_max, int64_t n) {
   const int kb = k_max <= 4 ? 4 : k_max <= 8 ? 8 : k_max <= 16 ? 16 : 64;
-  char buf[96];
-  snprintf(buf, sizeof(buf), "d%d_c%d_nn%d_k%d_n%d", d, (int)with_cand, bucket_log2(n_nodes), kb,
+  snprintf(buf, size, "d%d_c%d_nn%d_k%d_n%d", d, (int)with_cand, bucket_log2(n_nodes), kb,
            bucket_log2(n) / 2);
-  return buf;
 }
 
 void kc_tune_load(kc_handle *h) {
@@ -277,8 +274,10 @@ extern "C" kc_status kc_autotune(kc_handle *h, const kc_points *pts, const kc_no
     (void)hipFree(safe);
     (void)hipFree(am);
     (void)hipFree(cand);
-    h->err.clear();
-    h->tune[kc_tune_key(pts->d, wc, nn, nodes->k_max, pts->n)] = bt;
+    h->err[0] = 0;
+    char key[96];
+    kc_tune_key(key, sizeof(key), pts->d, wc, nn, nodes->k_max, pts->n);
+    h->tune[key] = bt;
     kc_tune_save(h);
     if (best_ms) *best_ms = best;
     return best < 1e30 ? KC_OK : kc_fail(h, KC_EDEVICE, "no variant ran");

@@ -1,5 +1,6 @@
 // kc_bound.hip -- kc_lower_bound / kc_objective entry points, launch sizing
 // and the kernels that reduce the per-split partial results.
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 
@@ -198,7 +199,8 @@ kc_tile kc_default_tile(kc_handle *h, int d, bool with_cand, int n_nodes, int k_
 kc_status kc_launch_bound(kc_handle *h, const kc_points *p, int mode, int n_nodes, int n_boxes,
                           int k_max, const int32_t *box_off, const float *lo, const float *hi,
                           float *val_raw, double *val_bound, int64_t *argmax, int64_t *cand,
-                          const kc_tile &t0, hipStream_t st) {
+                          const kc_tile &t0, hipStream_t st, void *fixed_scratch,
+                          size_t fixed_bytes) {
   const bool point = mode == 1;
   const bool with_cand = cand != nullptr && !point;
   kc_tile t = t0;
@@ -229,8 +231,16 @@ kc_status kc_launch_bound(kc_handle *h, const kc_points *p, int mode, int n_node
   const size_t part_bytes = (size_t)splits * n_nodes * 8;
   const size_t cand_bytes = with_cand ? (size_t)splits * n_boxes * 8 : 0;
   void *scr = nullptr;
-  kc_status s = kc_get_scratch(h, part_bytes + cand_bytes, &scr);
-  if (s != KC_OK) return s;
+  kc_status s = KC_OK;
+  if (fixed_scratch) {
+    KC_RETURN_IF(part_bytes + cand_bytes > fixed_bytes, h, KC_EINVAL,
+                 "request needs %zu bytes of scratch, above the %zu-byte static scratch of the "
+                 "no-allocation entry point (use fewer nodes or boxes per call)",
+                 part_bytes + cand_bytes, fixed_bytes);
+    scr = fixed_scratch;
+  } else if ((s = kc_get_scratch(h, part_bytes + cand_bytes, &scr)) != KC_OK) {
+    return s;
+  }
 
   BoundArgs A;
   A.x = p->x;
@@ -261,30 +271,81 @@ kc_status kc_launch_bound(kc_handle *h, const kc_points *p, int mode, int n_node
   return kc_check_launch(h, "k_bound_finalize");
 }
 
-static std::string tune_lookup_key(const kc_points *p, const kc_nodes *m, bool cand) {
-  return kc_tune_key(p->d, cand, m->n_nodes, m->k_max, p->n);
+// The tile for a lower-bound launch: the autotuner's choice for the shape
+// bucket, else the default (the key is built in a stack buffer and looked up
+// without allocating).
+static kc_tile lb_tile(kc_handle *h, const kc_points *p, const kc_nodes *m, bool cand) {
+  char key[96];
+  kc_tune_key(key, sizeof(key), p->d, cand, m->n_nodes, m->k_max, p->n);
+  auto it = h->tune.find(std::string_view(key));
+  if (it != h->tune.end()) return it->second;
+  return kc_default_tile(h, p->d, cand, m->n_nodes, m->k_max, p->n);
+}
+
+static kc_status lower_bound_impl(kc_handle *h, const kc_points *pts, const kc_nodes *nodes,
+                                  float *lb_raw, double *lb_safe, int64_t *argmax, int64_t *cand,
+                                  void *stream, void *fixed_scratch, size_t fixed_bytes) {
+  if (!h) return KC_EINVAL;
+  kc_status s = kc_validate_points(h, pts);
+  if (s != KC_OK) return s;
+  s = kc_validate_nodes(h, nodes, pts);
+  if (s != KC_OK) return s;
+  KC_RETURN_IF(!lb_raw && !lb_safe && !argmax && !cand, h, KC_EINVAL, "no output requested");
+  const bool wc = cand != nullptr;
+  const kc_tile t = lb_tile(h, pts, nodes, wc);
+  return kc_launch_bound(h, pts, 0, nodes->n_nodes, nodes->n_boxes, nodes->k_max, nodes->box_off,
+                         nodes->lo, nodes->hi, lb_raw, lb_safe, argmax, cand, t,
+                         (hipStream_t)stream, fixed_scratch, fixed_bytes);
 }
 
 extern "C" kc_status kc_lower_bound(kc_handle *h, const kc_points *pts, const kc_nodes *nodes,
                                     float *lb_raw, double *lb_safe, int64_t *argmax,
                                     int64_t *cand, void *stream) {
   return kc_guard(h, [&]() -> kc_status {
+    return lower_bound_impl(h, pts, nodes, lb_raw, lb_safe, argmax, cand, stream, nullptr, 0);
+  });
+}
+
+// ------------------------------------------- no-allocation lower bound ------
+// Scratch of kc_lower_bound_noalloc: the per-split partial keys of its
+// launches. Every GPU the library runs on holds its own copy until the
+// process ends. Host code never passes this name to a kernel (on the host it
+// is only a stand-in for the symbol): kernels get the device address that
+// hipGetSymbolAddress returns, kept per device below. No entry must start at
+// zero: every partial key the finalize kernel reads is written by the same
+// call's bound kernel first (for well-formed CSR offsets), so the previous
+// call's contents never matter. Calls that overlap on one GPU (different
+// streams, or several host threads) race on this array.
+static __device__ __align__(256) uint64_t scratch[KC_NOALLOC_SCRATCH_BYTES / 8];
+
+static constexpr int kMaxDevices = 64;
+static std::atomic<void *> g_scratch_addr[kMaxDevices];
+
+kc_status kc_noalloc_setup(kc_handle *h) {
+  KC_RETURN_IF(h->device < 0 || h->device >= kMaxDevices, h, KC_EUNSUPPORTED,
+               "device index %d beyond the no-allocation table", h->device);
+  void *p = g_scratch_addr[h->device].load();
+  if (!p) {
+    // h->device is the current device (kc_create set it)
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return kc_fail(h, KC_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    }
+    g_scratch_addr[h->device].store(p);
+  }
+  h->noalloc_scratch = p;
+  return KC_OK;
+}
+
+extern "C" kc_status kc_lower_bound_noalloc(kc_handle *h, const kc_points *pts,
+                                            const kc_nodes *nodes, float *lb_raw, double *lb_safe,
+                                            int64_t *argmax, int64_t *cand, void *stream) {
+  return kc_guard(h, [&]() -> kc_status {
     if (!h) return KC_EINVAL;
-    kc_status s = kc_validate_points(h, pts);
-    if (s != KC_OK) return s;
-    s = kc_validate_nodes(h, nodes, pts);
-    if (s != KC_OK) return s;
-    KC_RETURN_IF(!lb_raw && !lb_safe && !argmax && !cand, h, KC_EINVAL, "no output requested");
-    const bool wc = cand != nullptr;
-    kc_tile t;
-    auto it = h->tune.find(tune_lookup_key(pts, nodes, wc));
-    if (it != h->tune.end())
-      t = it->second;
-    else
-      t = kc_default_tile(h, pts->d, wc, nodes->n_nodes, nodes->k_max, pts->n);
-    return kc_launch_bound(h, pts, 0, nodes->n_nodes, nodes->n_boxes, nodes->k_max, nodes->box_off,
-                           nodes->lo, nodes->hi, lb_raw, lb_safe, argmax, cand, t,
-                           (hipStream_t)stream);
+    KC_RETURN_IF(!h->noalloc_scratch, h, KC_EDEVICE, "no static scratch on this device");
+    return lower_bound_impl(h, pts, nodes, lb_raw, lb_safe, argmax, cand, stream,
+                            h->noalloc_scratch, KC_NOALLOC_SCRATCH_BYTES);
   });
 }
 

@@ -9,6 +9,7 @@
 #include <map>
 #include <new>
 #include <string>
+#include <string_view>
 #include <vector>
 
 #include "kc.h"
@@ -24,11 +25,16 @@ struct kc_handle {
   int device = 0;
   int n_cu = 256;
   size_t lds_per_block = 65536;
-  std::string err;
+  char err[512] = {0};  // message of the last failure (no allocation on error paths)
   void *scratch = nullptr;
   size_t scratch_bytes = 0;
+  // device address of the static scratch array of kc_lower_bound_noalloc on
+  // this handle's device (taken once per device at kc_create)
+  void *noalloc_scratch = nullptr;
   std::string tune_path;
-  std::map<std::string, kc_tile> tune;  // shape bucket -> chosen tile
+  // shape bucket -> chosen tile; transparent comparator, so a lookup by a
+  // key in a stack buffer allocates nothing
+  std::map<std::string, kc_tile, std::less<>> tune;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   // flags and tile offsets of the last kc_reduce_count, for kc_reduce_compact
   struct {
@@ -66,14 +72,23 @@ kc_status kc_validate_refs(kc_handle *h, const kc_refs *r, const kc_nodes *m);
 
 // Bound-kernel launch (implemented in kc_bound.hip); `t` selects the variant.
 // mode 0: lower bound (optionally with candidates), mode 1: float32 objective.
+// fixed_scratch (nullable): device memory of fixed_bytes for the per-split
+// partial keys instead of the handle's scratch; a launch that needs more
+// fails with KC_EINVAL and allocates nothing.
 kc_status kc_launch_bound(kc_handle *h, const kc_points *pts, int mode, int n_nodes,
                           int n_boxes, int k_max, const int32_t *box_off, const float *lo,
                           const float *hi, float *val_raw, double *val_bound, int64_t *argmax,
-                          int64_t *cand, const kc_tile &t, hipStream_t st);
+                          int64_t *cand, const kc_tile &t, hipStream_t st,
+                          void *fixed_scratch = nullptr, size_t fixed_bytes = 0);
+// Takes the device address of kc_lower_bound_noalloc's static scratch array
+// for the current device (kc_bound.hip); called by kc_create with h->device
+// current.
+kc_status kc_noalloc_setup(kc_handle *h);
 // Variants compiled for this (d, with_cand) pair.
 std::vector<kc_tile> kc_bound_variants(int d, bool with_cand, int k_max);
 kc_tile kc_default_tile(kc_handle *h, int d, bool with_cand, int n_nodes, int k_max, int64_t n);
-std::string kc_tune_key(int d, bool with_cand, int n_nodes, int k_max, int64_t n);
+// Writes the autotune table key of a shape into buf (no allocation).
+void kc_tune_key(char *buf, size_t size, int d, bool with_cand, int n_nodes, int k_max, int64_t n);
 void kc_tune_load(kc_handle *h);
 void kc_tune_save(kc_handle *h);
 
