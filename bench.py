@@ -1,22 +1,26 @@
 #!/usr/bin/env python3
 """Benchmark of the K-center bound-evaluation hot path on one MI355X.
 
-Workload (default): N = 10^7 samples, D = 4, K = 5; a mixture of 5 Gaussians
-(std 0.1, means U[0,1]^4) plus 1% uniform outliers in [-0.5,1.5]^4, generated
-on the device from a fixed seed. One step runs the branch and bound from the
-root for a fixed number of batched passes (batch 64): root box, farthest-first
-traversal, seed test, per pass the tightening pass, sample reduction every two
-passes, the lower-bound pass over all children with their upper-bound
-candidates, the float32 objective screen and the float64 certificate of every
-improvement. The search is deterministic, so every step does identical work.
+Workload (default, mixture_1b_d2_k3): N = 10^9 samples, D = 2, K = 3; a
+mixture of 3 Gaussians (std 0.05, means U[0,1]^2), 8 GB of float32 samples
+generated on the device from a fixed seed. One step is one branch-and-bound
+solve to the certified optimum (batch 64, tightening with refs, sample
+reduction every pass, Morton order of the samples, tiles from the autotuner):
+root box, farthest-first traversal, seeds, per pass the tightening pass, the
+lower-bound pass over all children with their upper-bound candidates, the
+float32 objective screen and the float64 certificate of every improvement,
+until the gap is at most 1e-6. The warm-up solves fill the autotuner's table
+(the tile sweeps of new shapes run there, untimed).
 
-value = sample-box bound evaluations of the step / wall time of the step
-(inputs already resident in HBM). The roofline object describes the kernel
-with the largest share of the step (tightening or lower bound), timed with HIP
-events on the driver's stream; the CPU baseline times the float64 oracle's
-lower bound on a bounded sample.
+value = sample-box lower-bound evaluations of the step / wall time of the step
+(inputs resident in HBM); ms_per_step is the time to the certified optimum.
+The roofline object describes the kernel with the largest share of the step,
+timed with HIP events on the solver's stream; `kernels` adds the one-node
+lower-bound pass over all 10^9 samples against the HBM peak. The CPU baseline
+times the float64 oracle's lower bound on all host cores on a bounded sample
+of the same workload.
 
-Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload NAME]
 """
 from __future__ import annotations
 
@@ -39,7 +43,7 @@ WORKLOADS = {
     "mixture_10m_d4_k5": dict(n=10_000_000, d=4, k=5, std=0.1, outliers=0.01, seed=0,
                               batch=64, i_sr=2, passes=40),
     "mixture_1b_d2_k3": dict(n=1_000_000_000, d=2, k=3, std=0.05, outliers=0.0, seed=0,
-                             batch=64, i_sr=1, passes=None),
+                             batch=64, i_sr=1, passes=None, one_node_pass=True),
     # held-out instance of the learned-branching family (4 Gaussians, std 0.1,
     # 5 attributes): solve to the certified optimum with per-node carry-over,
     # capped at 120 s
@@ -59,7 +63,8 @@ WORKLOADS = {
 
 # the kernel's sources and the build script (its compiler flags), relative to csrc/
 KERNEL_SOURCES = {
-    "k_tighten": ["kc_tighten.hip", "kc_device.h", "kc_internal.h", "../build.py"],
+    "k_tighten": ["kc_tighten.hip", "kc_tighten_impl.h", "kc_device.h", "kc_internal.h",
+                  "../build.py"],
     "k_bound": ["kc_bound.hip", "kc_bound_impl.h", "kc_device.h", "kc_internal.h", "../build.py"],
 }
 
@@ -85,30 +90,38 @@ def profiled_traffic(kernel: str, workload: str):
     return float(m.group(1)) if hs.hexdigest() == h.group(1) else None
 
 
-def cpu_baseline(d: int, k: int, nodes: int, budget_s: float = 12.0):
-    """Float64 oracle lower bound (plain serial C) on a sample of the workload:
-    `nodes` nodes of k boxes over an increasing number of samples until the
-    time budget is spent; returns evals/s."""
+def _threads() -> int:
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def cpu_baseline(X64, off, lo64, hi64, what: str, budget_s: float = 12.0):
+    """The float64 oracle's lower bound (plain C, one call per chunk of the
+    samples, the chunks spread over all host cores) on a sample of the
+    workload, repeated until the time budget is spent; returns the record."""
+    import concurrent.futures as cf
+
     import numpy as np
 
-    import datagen
     import oracle
 
     oracle.lib()
-    X = datagen.gaussian_mixture(200_000, d, k, 0.1, 0, outlier_frac=0.01).astype(np.float64)
-    off, lo, hi = datagen.random_boxes(nodes, k, d, 0, wmin=0.01, wmax=0.5)
-    lo, hi = lo.astype(np.float64), hi.astype(np.float64)
-    n = 500
+    T = _threads()
+    n = len(X64)
+    step = (n + 4 * T - 1) // (4 * T)
+    parts = [(c, min(n, c + step)) for c in range(0, n, step)]
+    k = int(off[-1])
     evals, spent = 0, 0.0
-    while spent < budget_s:
-        t = time.perf_counter()
-        oracle.lower_bound(X[:n], off, lo, hi)
-        dt = time.perf_counter() - t
-        evals += n * nodes * k
-        spent += dt
-        if dt < budget_s / 10 and 2 * n <= len(X):
-            n *= 2
-    return evals / spent, f"oracle lower bound, {nodes} nodes x {k} boxes, up to {n} samples, {spent:.1f} s"
+    with cf.ThreadPoolExecutor(T) as ex:
+        while spent < budget_s:
+            t = time.perf_counter()
+            res = list(ex.map(lambda c: oracle.lower_bound(X64[c[0]:c[1]], off, lo64, hi64)[0], parts))
+            np.max(np.stack(res), axis=0)
+            spent += time.perf_counter() - t
+            evals += n * k
+    return {"value": evals / spent, "unit": "sample-box evals/s", "cores": T, "kind": "oracle",
+            "sample": f"{what}: oracle lower bound (float64, plain C) of {len(off) - 1} node(s) x "
+                      f"{k // (len(off) - 1)} boxes over {n} samples of the workload, in "
+                      f"{len(parts)} chunks on {T} threads, {spent:.1f} s"}
 
 
 def lb_pass(args, W) -> int:
@@ -125,13 +138,11 @@ def lb_pass(args, W) -> int:
     if nodes == 1:
         x = datagen.gaussian_mixture_device(n, d, k, W["std"], W["seed"], outlier_frac=W["outliers"])
         means = datagen._means(W["seed"], k, d).astype(np.float32)
-        off = torch.tensor([0, k], dtype=torch.int32, device="cuda")
-        lo = torch.from_numpy(means - 0.05).cuda()
-        hi = torch.from_numpy(means + 0.05).cuda()
+        o, l, h = np.array([0, k], dtype=np.int32), means - 0.05, means + 0.05
     else:
         x = datagen.uniform_points_device(n, d, W["seed"])
         o, l, h = datagen.random_boxes(nodes, k, d, W["seed"], wmin=1e-3, wmax=0.5)
-        off, lo, hi = (torch.from_numpy(a).cuda() for a in (o, l, h))
+    off, lo, hi = (torch.from_numpy(a).cuda() for a in (o, l, h))
     torch.empty_like(x).copy_(x)  # plain copy of known size (counter calibration)
     api.autotune(x, n, off, lo, hi, with_cand=False, k_max=k)
     for _ in range(args.warmup):
@@ -150,27 +161,29 @@ def lb_pass(args, W) -> int:
     tops = n * nodes * k * (3 * d + 1) / ker / 1e12  # algorithmic lane-ops
     per_set = None
     if nodes > 1 and args.box_seeds > 1:
-        # one timed launch per box set (seeds 0..N-1, each autotuned), median
+        # other box sets (seeds 1..N-1, each autotuned): the median over five
+        # timed launches per set, reported next to the headline's wall time
         per_set = []
-        for bs in range(args.box_seeds):
-            o, l, hh = datagen.random_boxes(nodes, k, d, bs, wmin=1e-3, wmax=0.5)
-            o2, l2, h2 = (torch.from_numpy(a).cuda() for a in (o, l, hh))
+        for bs in range(1, args.box_seeds):
+            o2, l2, h2 = (torch.from_numpy(a).cuda()
+                          for a in datagen.random_boxes(nodes, k, d, bs, wmin=1e-3, wmax=0.5))
             api.autotune(x, n, o2, l2, h2, with_cand=False, k_max=k)
             api.lower_bound(x, n, o2, l2, h2, k_max=k)
-            f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            f0.record()
-            api.lower_bound(x, n, o2, l2, h2, k_max=k)
-            f1.record()
-            torch.cuda.synchronize()
-            per_set.append(f0.elapsed_time(f1) / 1e3)
-        ker = float(np.median(per_set))
-        T = ker
-        tops = n * nodes * k * (3 * d + 1) / ker / 1e12
+            times = []
+            for _ in range(5):
+                f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                f0.record()
+                api.lower_bound(x, n, o2, l2, h2, k_max=k)
+                f1.record()
+                torch.cuda.synchronize()
+                times.append(f0.elapsed_time(f1) / 1e3)
+            per_set.append(float(np.median(times)))
     base = None
     if not args.no_cpu_baseline:
-        v, sample = cpu_baseline(d, k, min(nodes, 128))
-        base = {"value": v, "unit": "sample-box evals/s", "cores": 1, "kind": "oracle",
-                "sample": sample}
+        m = 4_000_000 if nodes == 1 else 200_000
+        X64 = x[:, :m].T.contiguous().cpu().numpy().astype(np.float64)
+        lo64, hi64 = l.astype(np.float64), h.astype(np.float64)
+        base = cpu_baseline(X64, o, lo64, hi64, "first samples of the workload")
     line = {
         "metric": "sample-box bound evals/s (% HBM peak); time to certified optimum, learned vs plain",
         "value": n * nodes * k / T, "unit": "sample-box evals/s", "n_gpus": 1, "steps": args.steps,
@@ -178,9 +191,8 @@ def lb_pass(args, W) -> int:
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "d": d, "k": k, "nodes": nodes,
                    "lb": float(lb_raw[0]), "argmax": int(am[0]), "kernel_ms_per_step": ker * 1e3,
-                   "box_sets": args.box_seeds if per_set else 1,
-                   "kernel_ms_per_box_set": [t * 1e3 for t in per_set] if per_set else None,
-                   "evals_per_kernel_second": n * nodes * k / ker},
+                   "evals_per_kernel_second": n * nodes * k / ker,
+                   "other_box_sets_kernel_ms_median_of_5": [t * 1e3 for t in per_set] if per_set else None},
         "roofline": ({"bound": "hbm", "kernel": "k_bound", "achieved": gbs, "peak": HBM_PEAK_GBS,
                       "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS} if nodes == 1 else
                      {"bound": "alu", "kernel": "k_bound", "achieved": tops, "peak": VALU_PEAK_TOPS,
@@ -192,25 +204,54 @@ def lb_pass(args, W) -> int:
     return 0
 
 
+def one_node_pass(x, n, d, k, seed, reps: int = 10):
+    """The one-node lower-bound pass (K boxes of side 0.1 around the mixture
+    means) over all samples: median of `reps` launches timed with HIP events
+    on the launch stream; returns (seconds, lb)."""
+    import numpy as np
+    import torch
+
+    import datagen
+    from paper_2301_00061_amd import api
+
+    means = datagen._means(seed, k, d).astype(np.float32)
+    off = torch.tensor([0, k], dtype=torch.int32, device="cuda")
+    lo, hi = torch.from_numpy(means - 0.05).cuda(), torch.from_numpy(means + 0.05).cuda()
+    api.autotune(x, n, off, lo, hi, with_cand=False, k_max=k)
+    api.lower_bound(x, n, off, lo, hi, k_max=k)
+    times = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        lb_raw, _, _, _ = api.lower_bound(x, n, off, lo, hi, k_max=k)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1) / 1e3)
+    return float(np.median(times)), float(lb_raw[0])
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="mixture_10m_d4_k5", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="mixture_1b_d2_k3", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--box-seeds", type=int, default=1,
-                    help="batched workload: time one launch for each of this many box sets "
-                         "(seeds 0..N-1) and report the median")
+                    help="batched workload: also time this many box sets (seeds 1..N-1, median "
+                         "of five launches each), reported next to the headline")
     ap.add_argument("--node-sr", type=int, default=None,
                     help="one-node sample reductions for nodes over at least this many samples "
                          "(0 = off; default: the workload's setting)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="solve with the default tiles (no tile sweeps in the warm-up)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: the library runs on one GPU; sharding the samples over several GPUs "
               "is described in the design notes but not implemented.", file=sys.stderr)
         return 2
 
+    import numpy as np
     import torch
 
     import datagen
@@ -223,20 +264,16 @@ def main() -> int:
     x = datagen.gaussian_mixture_device(W["n"], W["d"], W["k"], W["std"], W["seed"],
                                         outlier_frac=W["outliers"])
     torch.cuda.synchronize()
-    h = api.handle()
+    api.handle()
     n, k, d = W["n"], W["k"], W["d"]
     node_sr = args.node_sr if args.node_sr is not None else W.get("node_sr", 0)
     opts = dict(batch=W["batch"], i_sr=W["i_sr"], max_nodes=W["passes"] * W["batch"] if W["passes"] else 0,
-                node_sr=node_sr, time_limit_s=W.get("time_limit", 0.0))
+                node_sr=node_sr, time_limit_s=W.get("time_limit", 0.0),
+                autotune=not args.no_autotune)
 
     # one plain device copy of the points (known size: read and write
     # d * ld * 4 bytes), untimed: scales the profiler's HBM byte counters
     torch.empty_like(x).copy_(x)
-
-    # autotune the batched lower-bound shape of the driver (untimed set-up)
-    off, lo, hi = datagen.random_boxes(2 * W["batch"], k, d, 1, wmin=0.05, wmax=1.0)
-    dev = lambda a: torch.from_numpy(a).cuda()
-    api.autotune(x, n, dev(off), dev(lo), dev(hi), with_cand=True, k_max=k)
 
     for _ in range(args.warmup):
         api.solve(x, n, k, **opts)
@@ -262,8 +299,9 @@ def main() -> int:
     for v in kernels.values():
         v["achieved"] = v["evals"] * ops_per_eval / max(v["seconds"], 1e-12) / 1e12
         v["frac"] = v["achieved"] / VALU_PEAK_TOPS
-    dom = max(kernels, key=lambda k: kernels[k]["seconds"])
+    dom = max(kernels, key=lambda kk: kernels[kk]["seconds"])
     r0 = runs[0]
+    solve_s = [r["seconds"] for r in runs]
 
     # untimed: the same solve with the committed branching network (the
     # steps above use the max-range rule)
@@ -277,16 +315,27 @@ def main() -> int:
 
     # untimed: best objective of Algorithm 2 from 100 starts, the heuristic
     # the certified incumbent is compared with
-    import numpy as np
     starts = np.random.default_rng(0).integers(0, n, 100)
     _, fobj = api.fft(x, n, k, starts)
     fft100 = float(fobj.min())
 
+    # untimed: the one-node lower-bound pass over all samples (HBM roofline)
+    one = None
+    if W.get("one_node_pass"):
+        sec, lbv = one_node_pass(x, n, d, k, W["seed"])
+        gbs = n * d * 4 / sec / 1e9
+        one = {"what": "one node of K boxes (side 0.1 around the mixture means) over all samples",
+               "ms": sec * 1e3, "achieved_gbs": gbs, "peak_gbs": HBM_PEAK_GBS,
+               "frac": gbs / HBM_PEAK_GBS, "evals_per_s": n * k / sec, "lb": lbv,
+               "traffic": profiled_traffic("k_bound", "lb_1b_d2_k3")}
+
     base = None
     if not args.no_cpu_baseline:
-        v, sample = cpu_baseline(d, k, 2 * W["batch"])
-        base = {"value": v, "unit": "sample-box evals/s", "cores": 1, "kind": "oracle",
-                "sample": sample}
+        m = min(n, 4_000_000)
+        X64 = x[:, :m].T.contiguous().cpu().numpy().astype(np.float64)
+        means = datagen._means(W["seed"], k, d)
+        base = cpu_baseline(X64, np.array([0, k], dtype=np.int32), means - 0.05, means + 0.05,
+                            "the first samples of the workload, one node of K boxes around the means")
 
     line = {
         "metric": "sample-box bound evals/s (% HBM peak); time to certified optimum, learned vs plain",
@@ -304,20 +353,27 @@ def main() -> int:
         "config": {"workload": args.workload, "n": n, "d": d, "k": k,
                    "batch_nodes": W["batch"], "passes_per_step": W["passes"],
                    "sample_reduction_every": W["i_sr"], "node_sr": node_sr,
+                   "autotune": not args.no_autotune,
                    "node_sr_kept": r0["node_sr_kept"], "nodes_per_step": r0["nodes"],
-                   "gap_after_step": r0["gap"], "incumbent": r0["obj"],
-                   "certified_optimal": r0["status"] == 0, "solve_seconds": r0["seconds"],
+                   "gap_after_step": r0["gap"], "incumbent": r0["obj"], "lower_bound": r0["lb"],
+                   "certified_optimal": all(r["status"] == 0 for r in runs),
+                   "time_to_certified_optimum_s": (float(np.median(solve_s))
+                                                   if all(r["status"] == 0 for r in runs) else None),
+                   "solve_seconds": solve_s,
                    "fft100_best_obj": fft100, "ub_reduction_vs_fft100": (fft100 - r0["obj"]) / fft100,
-                   "lb_kernel_ms_per_step": lb_s * 1e3, "learned_rule": learned},
+                   "lb_kernel_ms_per_step": lb_s * 1e3, "tighten_kernel_ms_per_step": t_s * 1e3,
+                   "tighten_evals_per_step": t_evals, "learned_rule": learned},
         "roofline": {"bound": "alu", "kernel": dom, "achieved": kernels[dom]["achieved"],
                      "peak": VALU_PEAK_TOPS, "unit": "Tlane-op/s", "frac": kernels[dom]["frac"],
                      "traffic": profiled_traffic(dom, args.workload),
                      "share_of_step": kernels[dom]["seconds"] / T},
-        "kernels": {k: {"achieved_tlane_ops": v["achieved"], "frac": v["frac"],
-                        "ms_per_step": v["seconds"] * 1e3, "evals_per_step": v["evals"]}
-                    for k, v in kernels.items()},
+        "kernels": {kk: {"achieved_tlane_ops": v["achieved"], "frac": v["frac"],
+                         "ms_per_step": v["seconds"] * 1e3, "evals_per_step": v["evals"]}
+                    for kk, v in kernels.items()},
         "cpu_baseline": base,
     }
+    if one is not None:
+        line["kernels"]["k_bound_one_node_pass"] = one
     print(json.dumps(line))
     return 0
 

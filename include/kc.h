@@ -211,6 +211,16 @@ kc_status kc_reduce(kc_handle *h, const kc_points *in, const uint32_t *idx_in,
 kc_status kc_autotune(kc_handle *h, const kc_points *pts, const kc_nodes *nodes, int32_t with_cand,
                       double *best_ms, void *stream);
 
+/* Synchronous: times the compiled tiles of kc_tighten for this shape (samples
+ * per lane, nodes per workgroup sharing one load of the samples, occupancy),
+ * keeps the fastest in the handle's table (and the cache file) under the
+ * shape's bucket (attribute count, boxes per node, node and sample count
+ * buckets, with or without refs) and returns its time in milliseconds in
+ * *best_ms (host, nullable). Every tile gives bit-identical results. Its
+ * output buffers are allocated and freed inside the call. */
+kc_status kc_autotune_tighten(kc_handle *h, const kc_points *pts, const kc_nodes *nodes,
+                              double alpha, const kc_refs *refs, double *best_ms, void *stream);
+
 /* -------------------------------------------- branching network ---------- */
 /* A 32-64-64-64-1 ReLU network scoring (cluster, attribute) split candidates.
  * Weights: 10,497 values, layout W1[64][32] b1[64] W2[64][64] b2[64]
@@ -264,7 +274,12 @@ typedef struct {
                            at least a quarter of them. Tries are budgeted by
                            counted work; 65536 suits 10^6..10^9 samples;
                            0 = off                                          */
-  int32_t reserved1;
+  int32_t autotune;     /* 1: the first tightening and lower-bound launch of
+                           each shape bucket not yet in the handle's table
+                           runs the tile sweep (kc_autotune_tighten,
+                           kc_autotune) first; later launches and solves on
+                           the handle use the table. Results do not depend
+                           on the tile                                     */
   int64_t fft_start;    /* first FFT sample                                 */
   int64_t max_nodes;    /* 0 = unlimited                                    */
   double eps_rel;       /* relative gap at which to stop (>= 1e-6 advised)  */

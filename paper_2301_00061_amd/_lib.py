@@ -18,7 +18,7 @@ NOALLOC_SCRATCH_BYTES = 4 << 20  # KC_NOALLOC_SCRATCH_BYTES
 # every entry point declared in include/kc.h
 EXPORTS = [
     "kc_create", "kc_destroy", "kc_last_error", "kc_rel_margin", "kc_abs_margin",
-    "kc_lower_bound", "kc_lower_bound_noalloc", "kc_objective", "kc_fft", "kc_tighten", "kc_reduce", "kc_autotune",
+    "kc_lower_bound", "kc_lower_bound_noalloc", "kc_objective", "kc_fft", "kc_tighten", "kc_reduce", "kc_autotune", "kc_autotune_tighten",
     "kc_mlp_forward", "kc_mlp_backward", "kc_mlp_loss", "kc_mlp_adam", "kc_solve",
 ]
 
@@ -43,7 +43,7 @@ class Opts(C.Structure):
     _fields_ = [("k", C.c_int32), ("batch", C.c_int32), ("i_sr", C.c_int32),
                 ("use_bt", C.c_int32), ("use_seeds", C.c_int32), ("max_refs", C.c_int32),
                 ("branching", C.c_int32), ("keep_order", C.c_int32), ("node_sr", C.c_int32),
-                ("reserved1", C.c_int32), ("fft_start", C.c_int64), ("max_nodes", C.c_int64), ("eps_rel", C.c_double),
+                ("autotune", C.c_int32), ("fft_start", C.c_int64), ("max_nodes", C.c_int64), ("eps_rel", C.c_double),
                 ("time_limit_s", C.c_double), ("mlp_w", C.c_void_p), ("verbose", C.c_int32),
                 ("sb_first", C.c_int32), ("sb_every", C.c_int32), ("sb_cap", C.c_int32),
                 ("sb_feat", C.c_void_p), ("sb_score", C.c_void_p), ("sb_node", C.c_void_p),
@@ -102,6 +102,8 @@ def load(path: str = LIB_PATH):
                             vp, C.c_int64, vp, vp]
     L.kc_autotune.restype = st
     L.kc_autotune.argtypes = [vp, P(Points), P(Nodes), C.c_int32, P(C.c_double), vp]
+    L.kc_autotune_tighten.restype = st
+    L.kc_autotune_tighten.argtypes = [vp, P(Points), P(Nodes), C.c_double, P(Refs), P(C.c_double), vp]
     L.kc_mlp_forward.restype = st
     L.kc_mlp_forward.argtypes = [vp, vp, vp, C.c_int64, vp, vp, vp]
     L.kc_mlp_backward.restype = st

@@ -195,6 +195,20 @@ def fft(x, n, k, starts, h: Handle | None = None):
     return ids, obj
 
 
+def autotune_tighten(x, n, box_off, lo, hi, alpha, ref_off=None, ref=None, k_max=None,
+                     max_refs=None, h: Handle | None = None) -> float:
+    """Tile sweep of kc_tighten for this shape; returns the best time in ms."""
+    h = h or handle()
+    P = points(x, n)
+    M = nodes(box_off, lo, hi, k_max)
+    R = refs(ref_off, ref, max_refs)
+    ms = C.c_double()
+    h.check(h.lib.kc_autotune_tighten(h.ptr, C.byref(P), C.byref(M), float(alpha),
+                                      C.byref(R) if R is not None else None, C.byref(ms),
+                                      _stream()), "kc_autotune_tighten")
+    return ms.value
+
+
 def autotune(x, n, box_off, lo, hi, with_cand=False, k_max=None, h: Handle | None = None) -> float:
     h = h or handle()
     P = points(x, n)
@@ -247,7 +261,7 @@ def mlp_adam(w32, w_bf16, dw, m, v, step, lr, h: Handle | None = None):
 
 def solve(x, n, k, batch=64, i_sr=4, use_bt=True, use_seeds=True, max_refs=50, branching=0,
           fft_start=0, max_nodes=0, eps_rel=1e-6, time_limit_s=0.0, mlp_w=None, verbose=False,
-          sb=None, keep_order=False, node_sr=0, h: Handle | None = None) -> dict:
+          sb=None, keep_order=False, node_sr=0, autotune=False, h: Handle | None = None) -> dict:
     """Algorithm 1 on device-resident samples (synchronous)."""
     h = h or handle()
     P = points(x, n)
@@ -255,7 +269,7 @@ def solve(x, n, k, batch=64, i_sr=4, use_bt=True, use_seeds=True, max_refs=50, b
              max_refs=int(max_refs), branching=int(branching), fft_start=int(fft_start),
              max_nodes=int(max_nodes), eps_rel=float(eps_rel), time_limit_s=float(time_limit_s),
              mlp_w=mlp_w.data_ptr() if mlp_w is not None else None, verbose=int(verbose),
-             keep_order=int(bool(keep_order)), node_sr=int(node_sr))
+             keep_order=int(bool(keep_order)), node_sr=int(node_sr), autotune=int(bool(autotune)))
     if sb is not None:
         # strong-branching label recording into host arrays (see StrongBranchingBuffer)
         o.sb_first, o.sb_every, o.sb_cap = sb.first, sb.every, sb.cap

@@ -282,6 +282,12 @@ static kc_tile lb_tile(kc_handle *h, const kc_points *p, const kc_nodes *m, bool
   return kc_default_tile(h, p->d, cand, m->n_nodes, m->k_max, p->n);
 }
 
+bool kc_bound_tuned(kc_handle *h, const kc_points *p, const kc_nodes *m, bool cand) {
+  char key[96];
+  kc_tune_key(key, sizeof(key), p->d, cand, m->n_nodes, m->k_max, p->n);
+  return h->tune.find(std::string_view(key)) != h->tune.end();
+}
+
 static kc_status lower_bound_impl(kc_handle *h, const kc_points *pts, const kc_nodes *nodes,
                                   float *lb_raw, double *lb_safe, int64_t *argmax, int64_t *cand,
                                   void *stream, void *fixed_scratch, size_t fixed_bytes) {

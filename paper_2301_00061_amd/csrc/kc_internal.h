@@ -92,6 +92,14 @@ void kc_tune_key(char *buf, size_t size, int d, bool with_cand, int n_nodes, int
 void kc_tune_load(kc_handle *h);
 void kc_tune_save(kc_handle *h);
 
+// Tile of a tightening launch (kc_tighten.hip): the autotuner's choice for the
+// shape bucket (*tuned = true), else the default; kc_tile.bpc holds the
+// occupancy (wavefronts per SIMD, 0 = the compiler's choice).
+kc_tile kc_tighten_tile(kc_handle *h, const kc_points *pts, const kc_nodes *nodes,
+                        const kc_refs *refs, bool *tuned);
+// Whether the bound kernel's table holds a tile for this shape bucket.
+bool kc_bound_tuned(kc_handle *h, const kc_points *pts, const kc_nodes *nodes, bool cand);
+
 // Device gather of sample coordinates (kc_util.hip).
 kc_status kc_gather(kc_handle *h, const kc_points *p, const int64_t *ids, int count,
                     const uint32_t *idx_map, float *out, int64_t *orig, hipStream_t st);

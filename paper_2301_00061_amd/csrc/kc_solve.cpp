@@ -558,6 +558,17 @@ struct Solver {
     if (s) return s;
     for (size_t g = 0; g < R.size(); ++g) fill_boxes(plans[g], glo[g], ghi[g], o.use_bt ? &gnode[g] : nullptr);
     if ((s = upload())) return s;
+    if (o.autotune)  // shapes new to the handle's table: sweep the tiles first
+      for (size_t g = 0; g < R.size(); ++g) {
+        const kc_points p = pts_of(batch[R[g].first]);
+        const kc_nodes nd = dev_nodes(plans[g]);
+        const kc_refs rf = dev_refs(plans[g]);
+        bool tuned = false;
+        (void)kc_tighten_tile(h, &p, &nd, plans[g].refs ? &rf : nullptr, &tuned);
+        if (!tuned && (s = kc_autotune_tighten(h, &p, &nd, a_bt, plans[g].refs ? &rf : nullptr,
+                                               nullptr, st)))
+          return s;
+      }
     (void)hipEventRecord(h->ev0, st);
     for (size_t g = 0; g < R.size(); ++g) {
       const size_t i0 = (size_t)R[g].first, gn = (size_t)(R[g].second - R[g].first);
@@ -1357,6 +1368,13 @@ struct Solver {
     int64_t *ids = out.dp<int64_t>(o_ids);
     int64_t *orig = out.dp<int64_t>(o_orig);
     float *dxy = out.dp<float>(o_xy);
+    if (o.autotune)  // shapes new to the handle's table: sweep the tiles first
+      for (size_t g = 0; g < R.size(); ++g) {
+        const kc_points p = pts_of(ev[R[g].first]);
+        const kc_nodes nd = dev_nodes(plans[g]);
+        if (!kc_bound_tuned(h, &p, &nd, true) && (s = kc_autotune(h, &p, &nd, 1, nullptr, st)))
+          return s;
+      }
     (void)hipEventRecord(h->ev0, st);
     for (size_t g = 0; g < R.size(); ++g) {
       const size_t i0 = (size_t)R[g].first, gn = (size_t)(R[g].second - R[g].first);

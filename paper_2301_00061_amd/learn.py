@@ -198,7 +198,7 @@ def evaluate(seeds, n, k, wb, time_limit, batch=64, node_sr=0):
                           branching=1 if rule == "learned" else 0,
                           mlp_w=wb if rule == "learned" else None, node_sr=node_sr)
             res[rule] = dict(seconds=r["seconds"], nodes=r["nodes"], gap=r["gap"],
-                             solved=r["status"] == 0, obj=r["obj"])
+                             solved=r["status"] == 0, obj=r["obj"], lb=r["lb"])
         rows.append(dict(seed=seed, k=kk, n=n, **res))
         log(f"[eval] seed {seed} K={kk} plain {res['plain']['seconds']:.2f}s/{res['plain']['nodes']} "
             f"gap {res['plain']['gap']:.2e} | learned {res['learned']['seconds']:.2f}s/"
@@ -210,7 +210,13 @@ def evaluate(seeds, n, k, wb, time_limit, batch=64, node_sr=0):
         summ[rule] = dict(solved=sum(r[rule]["solved"] for r in rows),
                           sgm_seconds=shifted_geomean(ts),
                           sgm_nodes=shifted_geomean([r[rule]["nodes"] for r in rows]),
-                          mean_gap=float(np.mean([r[rule]["gap"] for r in rows])))
+                          mean_gap=float(np.mean([r[rule]["gap"] for r in rows])),
+                          mean_incumbent=float(np.mean([r[rule]["obj"] for r in rows])))
+    # per instance: which rule ends with the smaller gap / the better incumbent
+    summ["learned_smaller_gap"] = sum(r["learned"]["gap"] < r["plain"]["gap"] for r in rows)
+    summ["plain_smaller_gap"] = sum(r["plain"]["gap"] < r["learned"]["gap"] for r in rows)
+    summ["learned_better_incumbent"] = sum(r["learned"]["obj"] < r["plain"]["obj"] for r in rows)
+    summ["plain_better_incumbent"] = sum(r["plain"]["obj"] < r["learned"]["obj"] for r in rows)
     return rows, summ
 
 

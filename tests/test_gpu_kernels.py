@@ -590,3 +590,61 @@ def test_abi_rejects_malformed_requests(kc):
         rc = L.kc_tighten(hp, C.byref(P), C.byref(M), 1.0, C.byref(R), o, o, o, o, o, o, o, None,
                           None, None)
         assert rejected(rc), r
+
+
+def _tighten_tiles(d, k):
+    """The tightening kernel's compiled tiles (S, NG, wavefronts per SIMD) for
+    d attributes and k boxes per node, as its autotuner sweeps them."""
+    DM = d if d <= 8 else 16
+    kc = 1
+    for c in (1, 2, 3, 4, 5, 6, 8):
+        if c > (2 if d > 8 else 8) or c * (4 * DM + 4) > 160:
+            break
+        kc = c
+        if c >= k:
+            break
+    single = (k + kc - 1) // kc == 1
+    D = d if d <= 8 else 0
+    sd = 4 if 0 < D <= 4 else 2
+    md = 6 if D > 0 and D * kc <= 6 else 0
+    ma = 2 if md == 4 else 4
+    tiles = [(sd, 1, md), (sd, 1, ma), (sd // 2, 1, md)]
+    if single and D > 0 and D * kc <= 20:
+        tiles += [(sd, 2, 0), (sd // 2, 2, 0)]
+    if single and D > 0 and D * kc <= 8:
+        tiles += [(sd, 4, 0), (sd // 2, 4, 0)]
+    return tiles
+
+
+@pytest.mark.parametrize("seed,n,d,k,nn,with_refs", [
+    (30, 40000, 2, 3, 9, 7), (31, 30001, 2, 3, 5, False), (32, 20000, 4, 5, 7, 3),
+    (33, 15000, 5, 8, 3, 2), (34, 9000, 3, 2, 6, False), (35, 5000, 10, 2, 3, 1)])
+def test_tighten_every_tile_matches_default(kc, tmp_path, seed, n, d, k, nn, with_refs):
+    """Every tile the tightening autotuner can pick (read from a tune cache
+    file, one handle per tile) gives the default tile's outputs bit for bit,
+    and so does the tile the autotuner picks."""
+    X, off, lo, hi, alpha, ref_off, ref = _tighten_case(seed, n, d, k, nn, with_refs, 1.2, True)
+    xd = kc.to_device_soa(X)
+    dev = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    args = (xd, n, dev(off), dev(lo), dev(hi), alpha, dev(ref_off), dev(ref))
+    kw = dict(k_max=k, max_refs=int(with_refs) if with_refs else None)
+    keys = ("bb_lo", "bb_hi", "n_in", "asg_min", "asg_max", "n_asg", "n_excl", "asg_far")
+    ref_out = {key: v.cpu().numpy() for key, v in kc.tighten(*args, **kw).items() if key in keys}
+    assert ref_out["n_in"].sum() > 0
+    bn = int(np.log2(nn)) if nn > 1 else 0
+    bs = int(np.floor(np.log2(n))) // 2
+    key = f"t_d{d}_k{k}_nn{bn}_n{bs}_r{int(bool(with_refs))}"
+    for S, NG, mw in _tighten_tiles(d, k):
+        path = tmp_path / f"tune_{S}_{NG}_{mw}.txt"
+        path.write_text(f"{key} {S} {NG} {mw}\n")
+        h = kc.Handle(0, str(path))
+        out = kc.tighten(*args, **kw, h=h)
+        for name in keys:
+            assert np.array_equal(out[name].cpu().numpy(), ref_out[name]), (S, NG, mw, name)
+        h.close()
+    h = kc.Handle(0)
+    kc.autotune_tighten(*args, **kw, h=h)
+    out = kc.tighten(*args, **kw, h=h)
+    for name in keys:
+        assert np.array_equal(out[name].cpu().numpy(), ref_out[name]), name
+    h.close()
