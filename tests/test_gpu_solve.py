@@ -108,6 +108,12 @@ def test_solve_medium_instances(kc, seed):
     r = kc.solve(kc.to_device_soa(X), len(X), 3, batch=32, i_sr=2)
     assert r["status"] == 0
     _check(X64, r, ro["obj"])
+    # with the tiles the autotuner picks for each shape (tightening and bound)
+    h = kc.Handle(0)
+    r = kc.solve(kc.to_device_soa(X), len(X), 3, batch=32, i_sr=2, autotune=True, h=h)
+    h.close()
+    assert r["status"] == 0
+    _check(X64, r, ro["obj"])
 
 
 def test_solve_node_limit_keeps_valid_bounds(kc):
@@ -143,9 +149,13 @@ def test_spatial_order_keeps_the_certified_optimum():
     xd = api.to_device_soa(X)
     a = api.solve(xd, len(X), 3, batch=64, i_sr=2)
     b = api.solve(xd, len(X), 3, batch=64, i_sr=2, keep_order=True)
-    assert a["status"] == 0 and b["status"] == 0
+    h = api.Handle(0)
+    c = api.solve(xd, len(X), 3, batch=64, i_sr=2, autotune=True, h=h)
+    h.close()
+    assert a["status"] == 0 and b["status"] == 0 and c["status"] == 0
     assert abs(a["obj"] - b["obj"]) <= 1e-6 * b["obj"]
-    for r in (a, b):
+    assert abs(c["obj"] - b["obj"]) <= 1e-6 * b["obj"]
+    for r in (a, b, c):
         obj, _ = oracle.objective(X64, X64[r["centers"]][None])
         assert obj[0] == r["obj"] and r["lb"] <= r["obj"]
 
@@ -202,3 +212,30 @@ def test_node_reduction_large_instance(kc):
         assert obj[0] == r["obj"] and r["lb"] <= min(a["obj"], b["obj"]) * (1 + 1e-12)
     assert b["sb_rows"] > 0
     assert np.all(np.isfinite(sb.feat[:b["sb_rows"]])) and np.all(sb.score[:b["sb_rows"]] > 0)
+
+
+def _stored_oracle():
+    with open(os.path.join(GOLDEN, "oracle_solves.json")) as f:
+        return json.load(f)["cases"]
+
+
+@pytest.mark.parametrize("name", ["mixture_d2_k3_n1e6", "mixture_d4_k5_outliers_n2000",
+                                  "mixture_d5_k8_n300"])
+def test_solve_matches_stored_oracle_optimum(kc, name):
+    """Eq (1) on seeded instances of each workload family (the 10^9-sample
+    family: D = 2, K = 3; the 10^7-sample family: D = 4, K = 5 with 1%
+    outliers; the learned-branching family at K = 8, D = 5): the device's
+    certified optimum equals the oracle's (its branch and bound run to a zero
+    gap, stored by tests/golden/make_oracle_solves.py) within 1e-6."""
+    case = _stored_oracle()[name]
+    g = dict(case["generator"])
+    g.pop("function")
+    X = datagen.gaussian_mixture(**g)
+    X64 = X.astype(np.float64)
+    print(f"stored oracle case {name}: n={len(X)} k={case['k']}", flush=True)
+    r = kc.solve(kc.to_device_soa(X), len(X), case["k"], batch=64, i_sr=2, time_limit_s=100)
+    assert r["status"] == 0, r
+    _check(X64, r, case["obj"])
+    # the oracle's centers attain its value over the regenerated samples
+    obj, _ = oracle.objective(X64, X64[case["centers"]][None])
+    assert obj[0] == case["obj"]
