@@ -44,6 +44,13 @@ WORKLOADS = {
                               batch=64, i_sr=2, passes=40),
     "mixture_1b_d2_k3": dict(n=1_000_000_000, d=2, k=3, std=0.05, outliers=0.0, seed=0,
                              batch=64, i_sr=1, passes=None, one_node_pass=True),
+    # the same 10^7-sample instance solved toward the certified optimum: batch
+    # 256, per-node carry-over, capped at 300 s (the learned rule's solve is
+    # reported beside it, untimed); with --verbose the solver's progress lines
+    # (incumbent, lower bound, time) trace the gap over time
+    "mixture_10m_d4_k5_capped": dict(n=10_000_000, d=4, k=5, std=0.1, outliers=0.01, seed=0,
+                                     batch=256, i_sr=2, passes=None, node_sr=65536,
+                                     time_limit=300.0, learned=True),
     # held-out instance of the learned-branching family (4 Gaussians, std 0.1,
     # 5 attributes): solve to the certified optimum with per-node carry-over,
     # capped at 120 s
@@ -245,6 +252,8 @@ def main() -> int:
                          "(0 = off; default: the workload's setting)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="solve with the default tiles (no tile sweeps in the warm-up)")
+    ap.add_argument("--verbose", action="store_true",
+                    help="the solver's progress lines on stderr (nodes, incumbent, bound, time)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: the library runs on one GPU; sharding the samples over several GPUs "
@@ -269,7 +278,7 @@ def main() -> int:
     node_sr = args.node_sr if args.node_sr is not None else W.get("node_sr", 0)
     opts = dict(batch=W["batch"], i_sr=W["i_sr"], max_nodes=W["passes"] * W["batch"] if W["passes"] else 0,
                 node_sr=node_sr, time_limit_s=W.get("time_limit", 0.0),
-                autotune=not args.no_autotune)
+                autotune=not args.no_autotune, verbose=args.verbose)
 
     # one plain device copy of the points (known size: read and write
     # d * ld * 4 bytes), untimed: scales the profiler's HBM byte counters

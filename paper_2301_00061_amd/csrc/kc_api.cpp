@@ -205,18 +205,26 @@ void kc_tune_key(char *buf, size_t size, int d, bool with_cand, int n_nodes, int
            bucket_log2(n) / 2);
 }
 
+// Cache file: one line per shape bucket, "key S NG bpc [skip]".
 void kc_tune_load(kc_handle *h) {
   std::ifstream f(h->tune_path);
-  std::string key;
-  int S, NG, bpc;
-  while (f >> key >> S >> NG >> bpc) h->tune[key] = kc_tile{S, NG, bpc};
+  std::string line;
+  while (std::getline(f, line)) {
+    std::istringstream ls(line);
+    std::string key;
+    kc_tile t{};
+    if (!(ls >> key >> t.S >> t.NG >> t.bpc)) continue;
+    if (!(ls >> t.skip)) t.skip = 0;
+    h->tune[key] = t;
+  }
 }
 
 void kc_tune_save(kc_handle *h) {
   if (h->tune_path.empty()) return;
   std::ofstream f(h->tune_path, std::ios::trunc);
   for (auto &kv : h->tune)
-    f << kv.first << " " << kv.second.S << " " << kv.second.NG << " " << kv.second.bpc << "\n";
+    f << kv.first << " " << kv.second.S << " " << kv.second.NG << " " << kv.second.bpc << " "
+      << kv.second.skip << "\n";
 }
 
 extern "C" kc_status kc_autotune(kc_handle *h, const kc_points *pts, const kc_nodes *nodes,

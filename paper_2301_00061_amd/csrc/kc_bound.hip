@@ -7,15 +7,15 @@
 #include "kc_bound_impl.h"
 
 namespace kcb {
-kc_status launch_d0(int, int, int, bool, const BoundArgs &, int, size_t, hipStream_t);
-kc_status launch_d1(int, int, int, bool, const BoundArgs &, int, size_t, hipStream_t);
-kc_status launch_d2(int, int, int, bool, const BoundArgs &, int, size_t, hipStream_t);
-kc_status launch_d3(int, int, int, bool, const BoundArgs &, int, size_t, hipStream_t);
-kc_status launch_d4(int, int, int, bool, const BoundArgs &, int, size_t, hipStream_t);
-kc_status launch_d5(int, int, int, bool, const BoundArgs &, int, size_t, hipStream_t);
-kc_status launch_d6(int, int, int, bool, const BoundArgs &, int, size_t, hipStream_t);
-kc_status launch_d7(int, int, int, bool, const BoundArgs &, int, size_t, hipStream_t);
-kc_status launch_d8(int, int, int, bool, const BoundArgs &, int, size_t, hipStream_t);
+kc_status launch_d0(int, int, int, bool, int, const BoundArgs &, int, size_t, hipStream_t);
+kc_status launch_d1(int, int, int, bool, int, const BoundArgs &, int, size_t, hipStream_t);
+kc_status launch_d2(int, int, int, bool, int, const BoundArgs &, int, size_t, hipStream_t);
+kc_status launch_d3(int, int, int, bool, int, const BoundArgs &, int, size_t, hipStream_t);
+kc_status launch_d4(int, int, int, bool, int, const BoundArgs &, int, size_t, hipStream_t);
+kc_status launch_d5(int, int, int, bool, int, const BoundArgs &, int, size_t, hipStream_t);
+kc_status launch_d6(int, int, int, bool, int, const BoundArgs &, int, size_t, hipStream_t);
+kc_status launch_d7(int, int, int, bool, int, const BoundArgs &, int, size_t, hipStream_t);
+kc_status launch_d8(int, int, int, bool, int, const BoundArgs &, int, size_t, hipStream_t);
 kc_status launch_obj64_d0(const Obj64Args &, int, size_t, hipStream_t);
 kc_status launch_obj64_d1(const Obj64Args &, int, size_t, hipStream_t);
 kc_status launch_obj64_d2(const Obj64Args &, int, size_t, hipStream_t);
@@ -26,18 +26,18 @@ kc_status launch_obj64_d6(const Obj64Args &, int, size_t, hipStream_t);
 kc_status launch_obj64_d7(const Obj64Args &, int, size_t, hipStream_t);
 kc_status launch_obj64_d8(const Obj64Args &, int, size_t, hipStream_t);
 
-static kc_status dispatch(int d, int S, int NG, int KC, bool point, const BoundArgs &A, int grid,
-                          size_t lds, hipStream_t st) {
+static kc_status dispatch(int d, int S, int NG, int KC, bool point, int skip, const BoundArgs &A,
+                          int grid, size_t lds, hipStream_t st) {
   switch (d) {
-    case 1: return launch_d1(S, NG, KC, point, A, grid, lds, st);
-    case 2: return launch_d2(S, NG, KC, point, A, grid, lds, st);
-    case 3: return launch_d3(S, NG, KC, point, A, grid, lds, st);
-    case 4: return launch_d4(S, NG, KC, point, A, grid, lds, st);
-    case 5: return launch_d5(S, NG, KC, point, A, grid, lds, st);
-    case 6: return launch_d6(S, NG, KC, point, A, grid, lds, st);
-    case 7: return launch_d7(S, NG, KC, point, A, grid, lds, st);
-    case 8: return launch_d8(S, NG, KC, point, A, grid, lds, st);
-    default: return launch_d0(S, NG, KC, point, A, grid, lds, st);
+    case 1: return launch_d1(S, NG, KC, point, skip, A, grid, lds, st);
+    case 2: return launch_d2(S, NG, KC, point, skip, A, grid, lds, st);
+    case 3: return launch_d3(S, NG, KC, point, skip, A, grid, lds, st);
+    case 4: return launch_d4(S, NG, KC, point, skip, A, grid, lds, st);
+    case 5: return launch_d5(S, NG, KC, point, skip, A, grid, lds, st);
+    case 6: return launch_d6(S, NG, KC, point, skip, A, grid, lds, st);
+    case 7: return launch_d7(S, NG, KC, point, skip, A, grid, lds, st);
+    case 8: return launch_d8(S, NG, KC, point, skip, A, grid, lds, st);
+    default: return launch_d0(S, NG, KC, point, skip, A, grid, lds, st);
   }
 }
 
@@ -147,29 +147,61 @@ static int cand_kc(int k_max) {
 
 std::vector<kc_tile> kc_bound_variants(int d, bool with_cand, int k_max) {
   std::vector<kc_tile> v;
-  (void)d;
+  const bool ts = d >= 1 && d <= 8;  // tile decisions are compiled for 1..8 attributes
   if (with_cand) {
     const int kc = cand_kc(k_max);
 #define KCB_T3(SV, NGV, KCV) \
-  if (KCV == kc) v.push_back({SV, NGV, 8});
+  if (KCV == kc) v.push_back({SV, NGV, 8, 0});
     KCB_CAND_VARIANTS(KCB_T3)
 #undef KCB_T3
+#define KCB_T3S(SV, NGV, KCV) \
+  if (KCV == kc && ts) v.push_back({SV, NGV, 8, 1});
+    KCB_CAND_TS_VARIANTS(KCB_T3S)
+#undef KCB_T3S
   } else {
-#define KCB_T2(SV, NGV) v.push_back({SV, NGV, 8});
+#define KCB_T2(SV, NGV) v.push_back({SV, NGV, 8, 0});
     KCB_LB_VARIANTS(KCB_T2)
 #undef KCB_T2
+#define KCB_T2S(SV, NGV) \
+  if (ts) v.push_back({SV, NGV, 8, 1});
+    KCB_LB_TS_VARIANTS(KCB_T2S)
+#undef KCB_T2S
   }
   // each shape at two occupancies
   const size_t n0 = v.size();
-  for (size_t i = 0; i < n0; ++i) v.push_back({v[i].S, v[i].NG, 4});
+  for (size_t i = 0; i < n0; ++i) v.push_back({v[i].S, v[i].NG, 4, v[i].skip});
   return v;
 }
 
-static bool cand_compiled(int S, int NG, int KC) {
+static bool cand_compiled(int S, int NG, int KC, int skip, int d) {
+  if (skip) {
+    if (d < 1 || d > 8) return false;
+#define KCB_T4S(SV, NGV, KCV) \
+  if (S == SV && NG == NGV && KC == KCV) return true;
+    KCB_CAND_TS_VARIANTS(KCB_T4S)
+#undef KCB_T4S
+    return false;
+  }
 #define KCB_T4(SV, NGV, KCV) \
   if (S == SV && NG == NGV && KC == KCV) return true;
   KCB_CAND_VARIANTS(KCB_T4)
 #undef KCB_T4
+  return false;
+}
+
+static bool lb_compiled(int S, int NG, int skip, int d) {
+  if (skip) {
+    if (d < 1 || d > 8) return false;
+#define KCB_T5S(SV, NGV) \
+  if (S == SV && NG == NGV) return true;
+    KCB_LB_TS_VARIANTS(KCB_T5S)
+#undef KCB_T5S
+    return false;
+  }
+#define KCB_T5(SV, NGV) \
+  if (S == SV && NG == NGV) return true;
+  KCB_LB_VARIANTS(KCB_T5)
+#undef KCB_T5
   return false;
 }
 
@@ -182,7 +214,7 @@ static kc_tile cand_default(int n_nodes, int k_max) {
   if (kc == 8 && n_nodes >= 2) return {4, 2, 8};
   int ng = kc >= 64 ? 1 : 32 / kc;
   while (ng > 1 && ng / 2 >= n_nodes) ng /= 2;
-  while (ng > 1 && !cand_compiled(kc >= 16 ? 1 : 2, ng, kc)) ng /= 2;
+  while (ng > 1 && !cand_compiled(kc >= 16 ? 1 : 2, ng, kc, 0, 0)) ng /= 2;
   return {kc >= 16 ? 1 : 2, ng, 8};
 }
 
@@ -206,10 +238,15 @@ kc_status kc_launch_bound(kc_handle *h, const kc_points *p, int mode, int n_node
   kc_tile t = t0;
   const int DM = dmax_of(p->d);
   const int KC = with_cand ? cand_kc(k_max) : 0;
-  if (with_cand && !cand_compiled(t.S, t.NG, KC)) t = cand_default(n_nodes, k_max);
+  if (with_cand && !cand_compiled(t.S, t.NG, KC, t.skip, p->d)) t = cand_default(n_nodes, k_max);
+  if (!with_cand && !point && !lb_compiled(t.S, t.NG, t.skip, p->d))
+    t = kc_default_tile(h, p->d, false, n_nodes, k_max, p->n);
   if (point) {
-    if (!((t.S == 4 && t.NG == 1) || (t.S == 2 && t.NG == 4) || (t.S == 2 && t.NG == 8)))
-      t = n_nodes <= 2 ? kc_tile{4, 1, t.bpc} : kc_tile{2, 4, t.bpc};
+    // the float32 objective: (S, NG) of KCB_PT_VARIANTS, with tile decisions
+    // for 1..8 attributes
+    const bool ok = (t.S == 4 && t.NG == 1) || (t.S == 2 && t.NG == 4) || (t.S == 2 && t.NG == 8);
+    if (!ok) t = n_nodes <= 2 ? kc_tile{4, 1, t.bpc, t.skip} : kc_tile{2, 4, t.bpc, t.skip};
+    if (p->d < 1 || p->d > 8) t.skip = 0;
   }
   size_t lds = (size_t)t.NG * k_max * 2 * DM * sizeof(float);
   while (lds > h->lds_per_block && t.NG > 1) {
@@ -257,9 +294,9 @@ kc_status kc_launch_bound(kc_handle *h, const kc_points *p, int mode, int n_node
   A.span = span;
   A.part_key = (uint64_t *)scr;
   A.part_cand = with_cand ? (uint64_t *)((char *)scr + part_bytes) : nullptr;
-  s = dispatch(p->d, t.S, t.NG, KC, point, A, (int)grid, lds, st);
-  KC_RETURN_IF(s != KC_OK, h, s, "no bound-kernel variant S=%d NG=%d KC=%d point=%d", t.S, t.NG,
-               KC, (int)point);
+  s = dispatch(p->d, t.S, t.NG, KC, point, t.skip, A, (int)grid, lds, st);
+  KC_RETURN_IF(s != KC_OK, h, s, "no bound-kernel variant S=%d NG=%d KC=%d point=%d skip=%d", t.S,
+               t.NG, KC, (int)point, t.skip);
   s = kc_check_launch(h, "k_bound");
   if (s != KC_OK) return s;
   const int fin = n_nodes + (with_cand ? n_boxes : 0);
@@ -280,6 +317,74 @@ static kc_tile lb_tile(kc_handle *h, const kc_points *p, const kc_nodes *m, bool
   auto it = h->tune.find(std::string_view(key));
   if (it != h->tune.end()) return it->second;
   return kc_default_tile(h, p->d, cand, m->n_nodes, m->k_max, p->n);
+}
+
+// Tile of the float32 objective (point boxes): the autotuner's choice for the
+// shape bucket (attribute count, sets, centers per set, samples), else the
+// default.
+static void obj_key(char *buf, size_t size, int d, int n_sets, int k, int64_t n) {
+  int bn = 0, bs = 0;
+  for (int64_t v = n_sets; v > 1; v >>= 1) ++bn;
+  for (int64_t v = n; v > 1; v >>= 1) ++bs;
+  snprintf(buf, size, "o_d%d_ns%d_k%d_n%d", d, bn, k, bs / 2);
+}
+
+kc_tile kc_objective_tile(kc_handle *h, const kc_points *p, int n_sets, int k, bool *tuned) {
+  char key[96];
+  obj_key(key, sizeof(key), p->d, n_sets, k, p->n);
+  auto it = h->tune.find(std::string_view(key));
+  if (tuned) *tuned = it != h->tune.end();
+  if (it != h->tune.end()) return it->second;
+  return n_sets <= 2 ? kc_tile{4, 1, 8} : kc_tile{2, 4, 8};
+}
+
+kc_status kc_autotune_objective(kc_handle *h, const kc_points *p, int n_sets, int k,
+                                const float *centers, hipStream_t st) {
+  double *obj = nullptr;
+  int64_t *am = nullptr;
+  if (hipMalloc(&obj, (size_t)n_sets * 8) != hipSuccess ||
+      hipMalloc(&am, (size_t)n_sets * 8) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipFree(obj);
+    return kc_fail(h, KC_ENOMEM, "autotune output buffers");
+  }
+  std::vector<kc_tile> vars;
+  for (int skip = 0; skip <= (p->d >= 1 && p->d <= 8 ? 1 : 0); ++skip) {
+#define KCB_T6(SV, NGV) vars.push_back({SV, NGV, 8, skip});
+    KCB_PT_VARIANTS(KCB_T6)
+#undef KCB_T6
+  }
+  double best = 1e30;
+  kc_tile bt = kc_objective_tile(h, p, n_sets, k, nullptr);
+  kc_status s = KC_OK;
+  for (const kc_tile &t : vars) {
+    double tbest = 1e30;
+    for (int rep = 0; rep < 3 && s == KC_OK; ++rep) {
+      (void)hipEventRecord(h->ev0, st);
+      s = kc_launch_bound(h, p, 1, n_sets, n_sets * k, k, nullptr, centers, centers, nullptr, obj,
+                          am, nullptr, t, st);
+      (void)hipEventRecord(h->ev1, st);
+      if (s != KC_OK) break;
+      (void)hipEventSynchronize(h->ev1);
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, h->ev0, h->ev1);
+      if (rep > 0 && ms < tbest) tbest = ms;  // first run is a warm-up
+    }
+    if (s != KC_OK) break;
+    if (tbest < best) {
+      best = tbest;
+      bt = t;
+    }
+  }
+  (void)hipStreamSynchronize(st);
+  (void)hipFree(obj);
+  (void)hipFree(am);
+  if (s != KC_OK) return s;
+  char key[96];
+  obj_key(key, sizeof(key), p->d, n_sets, k, p->n);
+  h->tune[key] = bt;
+  kc_tune_save(h);
+  return KC_OK;
 }
 
 bool kc_bound_tuned(kc_handle *h, const kc_points *p, const kc_nodes *m, bool cand) {
@@ -369,7 +474,7 @@ extern "C" kc_status kc_objective(kc_handle *h, const kc_points *pts, int32_t n_
     KC_RETURN_IF(!obj && !argmax, h, KC_EINVAL, "no output requested");
     hipStream_t st = (hipStream_t)stream;
     if (precision == 32) {
-      kc_tile t = n_sets <= 2 ? kc_tile{4, 1, 8} : kc_tile{2, 4, 8};
+      const kc_tile t = kc_objective_tile(h, pts, n_sets, k, nullptr);
       return kc_launch_bound(h, pts, 1, n_sets, n_sets * k, k, nullptr, centers, centers, nullptr,
                              obj, argmax, nullptr, t, st);
     }

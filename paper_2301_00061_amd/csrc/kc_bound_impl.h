@@ -40,7 +40,10 @@ struct BoundArgs {
   uint64_t *part_cand;     // [splits][n_boxes] (candidate variants)
 };
 
-template <int D, int S, int NG, int KC, bool POINT>
+// TS: wavefront tiles (64 * S consecutive samples) that their bounding box
+// shows cannot raise a node's maximum nor hold a box's best candidate skip the
+// node's per-sample work (see below).
+template <int D, int S, int NG, int KC, bool POINT, bool TS = false>
 __global__ __launch_bounds__(WG) void k_bound(BoundArgs A) {
   constexpr int DM = D ? D : 16;
   constexpr int KCA = KC > 0 ? KC : 1;
@@ -103,9 +106,23 @@ __global__ __launch_bounds__(WG) void k_bound(BoundArgs A) {
     }
   }
 
+  // Tile decisions (TS): per node, W is a value the node's maximum over the
+  // samples already folded has reached (the largest lower bound of a tile's
+  // per-sample values so far), and lane k keeps in cw[jn] a distance to box
+  // k's midpoint that a sample inside the box already folded does not exceed.
+  float W[NG], cw[NG];
+#pragma unroll
+  for (int j = 0; j < NG; ++j) {
+    W[j] = -1.0f;
+    cw[j] = INFINITY;
+  }
+
   const int64_t s_lo = (int64_t)split * A.span;
   const int64_t s_hi = min(A.n, s_lo + A.span);
-  for (int64_t base = s_lo + (int64_t)tid * S; base < s_hi; base += (int64_t)WG * S) {
+  const int64_t lane_off = (int64_t)tid * S;
+  // with tile decisions every lane runs the same number of tiles
+  for (int64_t base = s_lo + lane_off; (TS ? base - lane_off : base) < s_hi;
+       base += (int64_t)WG * S) {
     float xv[DM][S];
     const bool full = base + S <= s_hi;
 #pragma unroll
@@ -140,11 +157,84 @@ __global__ __launch_bounds__(WG) void k_bound(BoundArgs A) {
       }
     }
 
+    float tlo[DM], thi[DM];
+    bool tile_empty = false;
+    if constexpr (TS) {
+      const int64_t wb = base - lane_off + (int64_t)wave * 64 * S;
+      tile_empty = wb >= s_hi;  // no sample of this wavefront lies in the split
+#pragma unroll
+      for (int a = 0; a < DM; ++a) {
+        float l = INFINITY, h = -INFINITY;
+        if (a < dd) {
+#pragma unroll
+          for (int i = 0; i < S; ++i)
+            if (base + i < s_hi) {
+              l = fminf(l, xv[a][i]);
+              h = fmaxf(h, xv[a][i]);
+            }
+        }
+        tlo[a] = __int_as_float(__builtin_amdgcn_readfirstlane(
+            __float_as_int(kcd::fdec(kcd::wave_min_u32(kcd::ford(l))))));
+        thi[a] = __int_as_float(__builtin_amdgcn_readfirstlane(
+            __float_as_int(kcd::fdec(kcd::wave_max_u32(kcd::ford(h))))));
+      }
+    }
+
 #pragma unroll
     for (int jn = 0; jn < NG; ++jn) {
       if (m0 + jn >= A.n_nodes) break;
       const float *bx = smem + jn * per_node;
       const int cnt = s_cnt[jn];
+      if constexpr (TS) {
+        if (tile_empty) continue;
+        // Lane k bounds, over the tile's range, the distance of box k (the
+        // per-sample operations in the same order on the tile's extreme
+        // coordinates; float32 rounding is monotone): every sample's value
+        // min_k lies in [lb_t, ub_t]. A tile with ub_t < W cannot raise the
+        // maximum (strictly below a value already reached, so not even a tie
+        // at a lower index). With candidates, a box the tile misses, or whose
+        // midpoint lies farther from the whole tile than cw, cannot get its
+        // candidate from the tile.
+        float lbk = INFINITY, ubk = INFINITY;
+        bool cskip = true;
+        if (lane < cnt) {
+          const float *B = bx + lane * 2 * DM;
+          float lb = 0.f, ub = 0.f, lm = 0.f, um = 0.f;
+          bool ia = true, inn = false;
+#pragma unroll
+          for (int a = 0; a < DM; ++a) {
+            if (a < dd) {
+              const float l = B[2 * a], h = POINT ? l : B[2 * a + 1];
+              const float gl = fmaxf(fmaxf(l - thi[a], tlo[a] - h), 0.f);
+              const float ul = fmaxf(fmaxf(l - tlo[a], thi[a] - h), 0.f);
+              lb = (a == 0) ? gl * gl : __builtin_fmaf(gl, gl, lb);
+              ub = (a == 0) ? ul * ul : __builtin_fmaf(ul, ul, ub);
+              if constexpr (KC > 0) {
+                const float mid = 0.5f * (l + h);
+                const float gm = fmaxf(fmaxf(mid - thi[a], tlo[a] - mid), 0.f);
+                const float um2 = fmaxf(thi[a] - mid, mid - tlo[a]);
+                lm = (a == 0) ? gm * gm : __builtin_fmaf(gm, gm, lm);
+                um = (a == 0) ? um2 * um2 : __builtin_fmaf(um2, um2, um);
+                ia = ia && l <= tlo[a] && thi[a] <= h;
+                inn = inn || thi[a] < l || tlo[a] > h;
+              }
+            }
+          }
+          lbk = lb;
+          ubk = ub;
+          if constexpr (KC > 0) {
+            cskip = inn || lm > cw[jn];
+            if (ia) cw[jn] = fminf(cw[jn], um);
+          }
+        }
+        const float lb_t = kcd::fdec(kcd::wave_min_u32(kcd::ford(lbk)));
+        const float ub_t = kcd::fdec(kcd::wave_min_u32(kcd::ford(ubk)));
+        const bool lb_skip = ub_t < W[jn];
+        W[jn] = fmaxf(W[jn], lb_t);
+        bool all_skip = lb_skip;
+        if constexpr (KC > 0) all_skip = all_skip && __ballot(!cskip) == 0;
+        if (all_skip) continue;
+      }
       float best[S];
 #pragma unroll
       for (int i = 0; i < S; ++i) best[i] = INFINITY;
@@ -345,9 +435,6 @@ __global__ __launch_bounds__(WG) void k_obj64(Obj64Args A) {
   }
 }
 
-kc_status launch_variant(int D, int S, int NG, int KC, bool point, const BoundArgs &A,
-                         int grid, size_t lds, hipStream_t st);
-
 }  // namespace kcb
 
 // Launch variants: (S, NG) for the lower bound and the float32 objective,
@@ -365,12 +452,44 @@ kc_status launch_variant(int D, int S, int NG, int KC, bool point, const BoundAr
 #define KCB_CAND_CASE(SV, NGV, KCV) \
   if (S == SV && NG == NGV && KC == KCV) { k_bound<DV_, SV, NGV, KCV, false><<<g, b, lds, st>>>(A); return KC_OK; }
 
+// Variants with tile decisions (attribute counts 1..8).
+#define KCB_LB_TS_VARIANTS(X) X(8, 1) X(4, 1) X(4, 4) X(4, 8) X(2, 8)
+#define KCB_PT_TS_VARIANTS(X) X(4, 1) X(2, 4) X(2, 8)
+#define KCB_CAND_TS_VARIANTS(X) X(2, 8, 4) X(2, 4, 4) X(4, 4, 4) X(4, 2, 8) X(2, 2, 8) X(2, 4, 8)
+#define KCB_LB_TS_CASE(SV, NGV) \
+  if (S == SV && NG == NGV) { k_bound<DV, SV, NGV, 0, false, true><<<g, b, lds, st>>>(A); return KC_OK; }
+#define KCB_PT_TS_CASE(SV, NGV) \
+  if (S == SV && NG == NGV) { k_bound<DV, SV, NGV, 0, true, true><<<g, b, lds, st>>>(A); return KC_OK; }
+#define KCB_CAND_TS_CASE(SV, NGV, KCV) \
+  if (S == SV && NG == NGV && KC == KCV) { k_bound<DV, SV, NGV, KCV, false, true><<<g, b, lds, st>>>(A); return KC_OK; }
+
+namespace kcb {
+template <int DV>
+inline kc_status launch_ts(int S, int NG, int KC, bool point, const BoundArgs &A, int grid,
+                           size_t lds, hipStream_t st) {
+  if constexpr (DV > 0) {
+    dim3 g(grid), b(WG);
+    if (point) {
+      KCB_PT_TS_VARIANTS(KCB_PT_TS_CASE)
+      return KC_EUNSUPPORTED;
+    }
+    if (KC > 0) {
+      KCB_CAND_TS_VARIANTS(KCB_CAND_TS_CASE)
+      return KC_EUNSUPPORTED;
+    }
+    KCB_LB_TS_VARIANTS(KCB_LB_TS_CASE)
+  }
+  return KC_EUNSUPPORTED;
+}
+}  // namespace kcb
+
 // Instantiates every variant for one attribute count (DV_ must be defined;
 // 0 = generic kernel for any d <= 16).
 #define KC_BOUND_DISPATCH(NAME, OBJNAME)                                                  \
   namespace kcb {                                                                        \
-  kc_status NAME(int S, int NG, int KC, bool point, const BoundArgs &A, int grid, size_t lds, \
-                 hipStream_t st) {                                                        \
+  kc_status NAME(int S, int NG, int KC, bool point, int skip, const BoundArgs &A, int grid,   \
+                 size_t lds, hipStream_t st) {                                            \
+    if (skip) return launch_ts<DV_>(S, NG, KC, point, A, grid, lds, st);                  \
     dim3 g(grid), b(WG);                                                                  \
     if (point) {                                                                          \
       KCB_PT_VARIANTS(KCB_PT_CASE)                                                        \

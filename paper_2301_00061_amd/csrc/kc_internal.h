@@ -16,9 +16,11 @@
 
 // One launch shape of the bound kernel.
 struct kc_tile {
-  int S;    // samples per lane per tile
-  int NG;   // nodes per workgroup (running maxima held in registers)
-  int bpc;  // workgroups per compute unit the grid is sized for
+  int S;         // samples per lane per tile
+  int NG;        // nodes per workgroup (running maxima held in registers)
+  int bpc;       // workgroups per compute unit the grid is sized for (bound
+                 // kernel) / wavefronts per SIMD (tightening kernel)
+  int skip = 0;  // tightening: wavefront tiles settled from their bounding box
 };
 
 struct kc_handle {
@@ -99,6 +101,11 @@ kc_tile kc_tighten_tile(kc_handle *h, const kc_points *pts, const kc_nodes *node
                         const kc_refs *refs, bool *tuned);
 // Whether the bound kernel's table holds a tile for this shape bucket.
 bool kc_bound_tuned(kc_handle *h, const kc_points *pts, const kc_nodes *nodes, bool cand);
+// Tile of the float32 objective (kc_objective precision 32) for n_sets sets of
+// k centers, and its sweep (kc_bound.hip; synchronous, allocates its outputs).
+kc_tile kc_objective_tile(kc_handle *h, const kc_points *pts, int n_sets, int k, bool *tuned);
+kc_status kc_autotune_objective(kc_handle *h, const kc_points *pts, int n_sets, int k,
+                                const float *centers, hipStream_t st);
 
 // Device gather of sample coordinates (kc_util.hip).
 kc_status kc_gather(kc_handle *h, const kc_points *p, const int64_t *ids, int count,

@@ -212,7 +212,6 @@ struct Solver {
   double t0 = 0;
   // wall time per phase (reported with verbose)
   double t_tighten = 0, t_reduce = 0, t_branch = 0, t_bound = 0;
-  double last_pass_s = 0;  // wall time of the previous pass without its reduction
   int64_t sr_interval = 0, sr_runs = 0;
   int64_t n_bounded = 0, n_bounded_pruned = 0;  // bounded nodes, and those the bound prunes
   // subtree sample sets: bytes held and the cap on them; measured cost of a
@@ -665,6 +664,38 @@ struct Solver {
   }
 
   // ---------------------------------------------------- sample reduction --
+  // Whether the reduction over the open nodes and `extra` can delete any
+  // sample. A sample is LB-redundant in a node (Section 4.2.1) only if its
+  // farthest-corner distance to some box is below beta, the least lower
+  // bound; from any point the farthest corner of a box is at least half its
+  // diagonal away, so a node none of whose boxes has a squared half-diagonal
+  // below beta keeps every sample (and the reduction keeps what any node
+  // keeps).
+  bool can_reduce(const std::vector<Node *> &extra) const {
+    const double thr = prune_thr();
+    double beta = INFINITY;
+    for (const Node *m : heap)
+      if (m->lb < thr) beta = std::min(beta, m->lb);
+    for (const Node *m : extra) beta = std::min(beta, m->lb);
+    if (!(beta > 0) || !std::isfinite(beta)) return false;
+    auto small_box = [&](const Node *m) {
+      for (int k = 0; k < K; ++k) {
+        double r2 = 0;
+        for (int a = 0; a < D; ++a) {
+          const double hw = 0.5 * ((double)m->hi[k * D + a] - m->lo[k * D + a]);
+          r2 += hw * hw;
+        }
+        if (r2 * (1.0 - 1e-12) < beta) return true;
+      }
+      return false;
+    };
+    for (const Node *m : extra)
+      if (!small_box(m)) return false;
+    for (const Node *m : heap)
+      if (m->lb < thr && !small_box(m)) return false;
+    return true;
+  }
+
   // Over every open node, so the active samples stay valid for all of them;
   // a subtree set no smaller than the result is then dropped.
   kc_status reduce(const std::vector<Node *> &extra) {
@@ -1158,9 +1189,7 @@ struct Solver {
       // bounds tightening
       const double a_bt = o.use_bt ? alpha_ub : INFINITY;
       double tp = now_s();
-      const double pass_start = tp;
       const int64_t evals_start = res->evals + res->tighten_evals;
-      double sr_cost = 0;
       if ((s = tighten(batch, alive, a_bt))) return s;
       t_tighten += now_s() - tp;
       std::vector<Node *> live;
@@ -1175,24 +1204,25 @@ struct Solver {
         }
       }
       // sample reduction every i_sr passes, over the open nodes and this
-      // batch. A reduction that deletes under 1% of the active samples and
-      // costs more than a quarter of a pass doubles the interval (up to
-      // 64 i_sr); any other resets it to i_sr.
+      // batch, when it can delete anything (can_reduce); otherwise it is
+      // tried again at the next pass. A reduction that deletes under 1% of
+      // the active samples doubles the interval (up to 64 i_sr), any other
+      // resets it to i_sr. The rules count samples and box sizes, not time,
+      // so the schedule of a solve does not depend on kernel speed.
       ++passes_since_sr;
       if (o.i_sr > 0 && sr_interval == 0) sr_interval = o.i_sr;
-      if (o.i_sr > 0 && passes_since_sr >= sr_interval) {
+      if (o.i_sr > 0 && passes_since_sr >= sr_interval && can_reduce(live)) {
         passes_since_sr = 0;
         tp = now_s();
         const int64_t before = act.n;
         if ((s = reduce(live))) return s;
         ++sr_runs;
         const double cost = now_s() - tp;
-        if ((double)(before - act.n) < 0.01 * (double)before && cost > 0.25 * last_pass_s)
+        if ((double)(before - act.n) < 0.01 * (double)before)
           sr_interval = std::min<int64_t>(sr_interval * 2, (int64_t)o.i_sr * 64);
         else
           sr_interval = o.i_sr;
         t_reduce += cost;
-        sr_cost = cost;
       }
       tp = now_s();
 
@@ -1238,7 +1268,6 @@ struct Solver {
           }
         }
         t_reduce += now_s() - tn;
-        sr_cost += now_s() - tn;
         tp += now_s() - tn;
       }
       std::vector<int> ck, ca;
@@ -1305,7 +1334,6 @@ struct Solver {
       if (!ev.empty())
         if ((s = bound(ev, is_leaf))) return s;
       t_bound += now_s() - tp;
-      last_pass_s = now_s() - pass_start - sr_cost;
       last_pass_evals = res->evals + res->tighten_evals - evals_start;
 
       if (!heap.empty()) {
@@ -1400,6 +1428,12 @@ struct Solver {
       // sample 0 in its place; its value is never used); over the node's
       // samples it equals the objective over all samples, since a deleted
       // sample lies closer than the node's bound to any centers in its boxes
+      if (o.autotune) {  // a shape new to the handle's table: sweep the tiles first
+        bool tuned = false;
+        (void)kc_objective_tile(h, &p, (int)gn, K, &tuned);
+        if (!tuned && (s = kc_autotune_objective(h, &p, (int)gn, K, dxy + i0 * K * D, st)))
+          return s;
+      }
       s = kc_objective(h, &p, (int)gn, K, dxy + i0 * K * D, 32, out.dp<double>(o_obj) + i0,
                        out.dp<int64_t>(o_oam) + i0, st);
       if (s) return s;

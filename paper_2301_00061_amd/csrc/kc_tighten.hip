@@ -8,28 +8,28 @@
 #include "kc_tighten_impl.h"
 
 namespace kct {
-bool launch_tighten_d0(int, int, int, int, bool, const TightenArgs &, int, size_t, hipStream_t);
-bool launch_tighten_d1(int, int, int, int, bool, const TightenArgs &, int, size_t, hipStream_t);
-bool launch_tighten_d2(int, int, int, int, bool, const TightenArgs &, int, size_t, hipStream_t);
-bool launch_tighten_d3(int, int, int, int, bool, const TightenArgs &, int, size_t, hipStream_t);
-bool launch_tighten_d4(int, int, int, int, bool, const TightenArgs &, int, size_t, hipStream_t);
-bool launch_tighten_d5(int, int, int, int, bool, const TightenArgs &, int, size_t, hipStream_t);
-bool launch_tighten_d6(int, int, int, int, bool, const TightenArgs &, int, size_t, hipStream_t);
-bool launch_tighten_d7(int, int, int, int, bool, const TightenArgs &, int, size_t, hipStream_t);
-bool launch_tighten_d8(int, int, int, int, bool, const TightenArgs &, int, size_t, hipStream_t);
+bool launch_tighten_d0(int, int, int, int, int, bool, const TightenArgs &, int, size_t, hipStream_t);
+bool launch_tighten_d1(int, int, int, int, int, bool, const TightenArgs &, int, size_t, hipStream_t);
+bool launch_tighten_d2(int, int, int, int, int, bool, const TightenArgs &, int, size_t, hipStream_t);
+bool launch_tighten_d3(int, int, int, int, int, bool, const TightenArgs &, int, size_t, hipStream_t);
+bool launch_tighten_d4(int, int, int, int, int, bool, const TightenArgs &, int, size_t, hipStream_t);
+bool launch_tighten_d5(int, int, int, int, int, bool, const TightenArgs &, int, size_t, hipStream_t);
+bool launch_tighten_d6(int, int, int, int, int, bool, const TightenArgs &, int, size_t, hipStream_t);
+bool launch_tighten_d7(int, int, int, int, int, bool, const TightenArgs &, int, size_t, hipStream_t);
+bool launch_tighten_d8(int, int, int, int, int, bool, const TightenArgs &, int, size_t, hipStream_t);
 
-static bool dispatch(int d, int kc, int S, int NG, int minw, bool refs, const TightenArgs &A,
-                     int grid, size_t lds, hipStream_t st) {
+static bool dispatch(int d, int kc, int S, int NG, int minw, int skip, bool refs,
+                     const TightenArgs &A, int grid, size_t lds, hipStream_t st) {
   switch (d) {
-    case 1: return launch_tighten_d1(kc, S, NG, minw, refs, A, grid, lds, st);
-    case 2: return launch_tighten_d2(kc, S, NG, minw, refs, A, grid, lds, st);
-    case 3: return launch_tighten_d3(kc, S, NG, minw, refs, A, grid, lds, st);
-    case 4: return launch_tighten_d4(kc, S, NG, minw, refs, A, grid, lds, st);
-    case 5: return launch_tighten_d5(kc, S, NG, minw, refs, A, grid, lds, st);
-    case 6: return launch_tighten_d6(kc, S, NG, minw, refs, A, grid, lds, st);
-    case 7: return launch_tighten_d7(kc, S, NG, minw, refs, A, grid, lds, st);
-    case 8: return launch_tighten_d8(kc, S, NG, minw, refs, A, grid, lds, st);
-    default: return launch_tighten_d0(kc, S, NG, minw, refs, A, grid, lds, st);
+    case 1: return launch_tighten_d1(kc, S, NG, minw, skip, refs, A, grid, lds, st);
+    case 2: return launch_tighten_d2(kc, S, NG, minw, skip, refs, A, grid, lds, st);
+    case 3: return launch_tighten_d3(kc, S, NG, minw, skip, refs, A, grid, lds, st);
+    case 4: return launch_tighten_d4(kc, S, NG, minw, skip, refs, A, grid, lds, st);
+    case 5: return launch_tighten_d5(kc, S, NG, minw, skip, refs, A, grid, lds, st);
+    case 6: return launch_tighten_d6(kc, S, NG, minw, skip, refs, A, grid, lds, st);
+    case 7: return launch_tighten_d7(kc, S, NG, minw, skip, refs, A, grid, lds, st);
+    case 8: return launch_tighten_d8(kc, S, NG, minw, skip, refs, A, grid, lds, st);
+    default: return launch_tighten_d0(kc, S, NG, minw, skip, refs, A, grid, lds, st);
   }
 }
 
@@ -91,21 +91,19 @@ static std::vector<kc_tile> tighten_variants(int d, int kc, bool single) {
   const int SD = D > 0 && D <= 4 ? 4 : 2;
   const int MD = D > 0 && D * kc <= 6 ? 6 : 0;
   const int MA = MD == 4 ? 2 : 4;
-  std::vector<kc_tile> v{{SD, 1, MD}, {SD, 1, MA}, {SD / 2, 1, MD}};
-  if (single && D > 0 && D * kc <= 20) {
-    v.push_back({SD, 2, 0});
-    v.push_back({SD / 2, 2, 0});
-  }
-  if (single && D > 0 && D * kc <= 8) {
-    v.push_back({SD, 4, 0});
-    v.push_back({SD / 2, 4, 0});
+  std::vector<kc_tile> v{{SD, 1, MD, 0}, {SD, 1, MA, 0}, {SD / 2, 1, MD, 0}};
+  if (single && D > 0 && D * kc <= 20) v.push_back({SD, 2, 0, 0});
+  if (single && D > 0) {
+    for (int m : {1, 2, 4}) v.push_back({m * SD, 1, 0, 1});
+    if (D * kc <= 20)
+      for (int m : {1, 2}) v.push_back({m * SD, 2, 0, 1});
   }
   return v;
 }
 
 static bool tile_ok(int d, int kc, bool single, const kc_tile &t) {
   for (const kc_tile &v : tighten_variants(d, kc, single))
-    if (v.S == t.S && v.NG == t.NG && v.bpc == t.bpc) return true;
+    if (v.S == t.S && v.NG == t.NG && v.bpc == t.bpc && v.skip == t.skip) return true;
   return false;
 }
 
@@ -216,7 +214,7 @@ static kc_status run(kc_handle *h, Launch &L, float *bb_lo, float *bb_hi,
   A.asg_far = (uint64_t *)asg_far;
   A.labels = labels;
   const kc_tile &t = L.t;
-  KC_RETURN_IF(!dispatch(A.d, L.kc, t.S, t.NG, t.bpc, L.refs, A, L.grid, L.lds, st), h,
+  KC_RETURN_IF(!dispatch(A.d, L.kc, t.S, t.NG, t.bpc, t.skip, L.refs, A, L.grid, L.lds, st), h,
                KC_EUNSUPPORTED, "no tighten variant for d=%d kc=%d S=%d NG=%d", A.d, L.kc, t.S, t.NG);
   s = kc_check_launch(h, "k_tighten");
   if (s != KC_OK) return s;
@@ -304,7 +302,8 @@ extern "C" kc_status kc_autotune_tighten(kc_handle *h, const kc_points *pts, con
       Launch L;
       s = plan(h, pts, nodes, alpha, refs, false, t, L);
       if (s != KC_OK) break;
-      if (L.t.S != t.S || L.t.NG != t.NG || L.t.bpc != t.bpc) continue;  // did not fit LDS
+      if (L.t.S != t.S || L.t.NG != t.NG || L.t.bpc != t.bpc || L.t.skip != t.skip)
+        continue;  // did not fit LDS
       double tbest = 1e30;
       for (int rep = 0; rep < 3 && s == KC_OK; ++rep) {
         (void)hipEventRecord(h->ev0, st);

@@ -105,14 +105,215 @@ struct NodeSlot {
   int rbeg[64], rcnt[64];
 };
 
+// Whether every sample of the tile lies within squared distance t of every
+// one of the rc refs at r0 (*all) or no sample does (*none), one lane per ref:
+// the bounds over the tile are those of sqdist on the tile's extreme
+// coordinates.
+template <int DM>
+__device__ __forceinline__ void refs_class(const float *r0, int rc, float t, const float (&tlo)[DM],
+                                           const float (&thi)[DM], int dd, int lane, bool &all,
+                                           bool &none) {
+  bool f = true, n = false;
+  if (lane < rc) {
+    const float *r = r0 + lane * DM;
+    float rn = 0.f, rx = 0.f;
+#pragma unroll
+    for (int a = 0; a < DM; ++a) {
+      if (a < dd) {
+        const float g = fmaxf(fmaxf(r[a] - thi[a], tlo[a] - r[a]), 0.f);
+        const float u = fmaxf(thi[a] - r[a], r[a] - tlo[a]);
+        rn = (a == 0) ? g * g : __builtin_fmaf(g, g, rn);
+        rx = (a == 0) ? u * u : __builtin_fmaf(u, u, rx);
+      }
+    }
+    f = rx <= t;
+    n = rn > t;
+  }
+  all = __ballot(!f) == 0;
+  none = __ballot(n) != 0;
+}
+
+// One node and one wavefront tile (64 * S consecutive samples, nval of them
+// in the split, bounding box [tlo, thi]) settled from the bounding box alone
+// where it can be. Lane k classifies box k of the node (whether every or no
+// sample of the tile is excluded from the box's cluster by the center-based
+// test, or lies inside the box); where the label needs the sample-based test
+// and for each box the tile meets, lane r classifies ref r of the box
+// (whether every or no sample lies within 4 alpha, resp. alpha, of every
+// ref). The bounds over the tile are formed with the per-sample operations in
+// the same order, on the tile's extreme coordinates, and float32 rounding is
+// monotone, so a bound on the safe side of a threshold gives every sample's
+// test the same outcome. When every sample gets the same label, the label's
+// aggregates take the tile's bounding box and count (the farthest-from-
+// midpoint key runs per sample unless the tile lies nearer the midpoint than
+// an earlier tile of the label: fw holds the least distance of such tiles),
+// S_+ aggregates of boxes the tile settles likewise, and only the unsettled
+// boxes' S_+ tests run per sample. Returns false (nothing updated) when the
+// labels differ within the tile; the per-sample path then runs.
+template <int D, int KC, int S, bool REFS>
+__device__ __forceinline__ bool tile_node(
+    const TightenArgs &A, const float (&xs)[S][D ? D : 16], int64_t base, int64_t s_hi, int nval,
+    const float (&tlo)[D ? D : 16], const float (&thi)[D ? D : 16], const float *bx,
+    const float *rbx, const float *rf, const NodeSlot &ns, int cnt, bool allref, int lane,
+    bool write_labels, uint32_t &nex, uint32_t (&nin)[KC], uint32_t (&nasg)[KC],
+    uint64_t (&far)[KC], float (&fw)[KC], float (&bmin)[KC][D ? D : 16],
+    float (&bmax)[KC][D ? D : 16], float (&amin)[KC][D ? D : 16], float (&amax)[KC][D ? D : 16]) {
+  constexpr int DM = D ? D : 16;
+  const int dd = D ? D : A.d;
+  bool c_out = false, c_keep = false, in_all = false, in_none = false;
+  if (lane < cnt) {
+    const float *B = bx + lane * 2 * DM;
+    float lb = 0.f, ub = 0.f;
+    bool ia = true, inn = false;
+#pragma unroll
+    for (int a = 0; a < DM; ++a) {
+      if (a < dd) {
+        const float lo = B[2 * a], hi = B[2 * a + 1];
+        // least and greatest distance to [lo, hi] over the tile's range
+        const float g = fmaxf(fmaxf(lo - thi[a], tlo[a] - hi), 0.f);
+        const float u = fmaxf(fmaxf(lo - tlo[a], thi[a] - hi), 0.f);
+        lb = (a == 0) ? g * g : __builtin_fmaf(g, g, lb);
+        ub = (a == 0) ? u * u : __builtin_fmaf(u, u, ub);
+        ia = ia && lo <= tlo[a] && thi[a] <= hi;
+        inn = inn || thi[a] < lo || tlo[a] > hi;
+      }
+    }
+    c_out = lb > A.t_center;
+    c_keep = !(ub > A.t_center);
+    in_all = ia;
+    in_none = inn;
+  }
+  const uint64_t vm = cnt >= 64 ? ~0ull : ((1ull << cnt) - 1ull);
+  const uint64_t m_out = __ballot(c_out) & vm, m_keep = __ballot(c_keep) & vm;
+  if ((m_out | m_keep) != vm) return false;  // a center-based test differs within the tile
+  const int n_out = __popcll(m_out);
+  int lab;
+  if (n_out == cnt) {
+    lab = -2;
+  } else if (n_out == cnt - 1) {
+    lab = __ffsll((unsigned long long)(vm & ~m_out)) - 1;
+  } else {
+    lab = -1;
+    if (REFS && allref) {
+      // sample-based assignment: exactly one cluster with every ref within
+      // 4 alpha gives the label (the per-sample scan stops at two)
+      int near = 0, first = -1;
+      bool mixed = false;
+      for (int k = 0; k < cnt && near < 2; ++k) {
+        bool all, none;
+        refs_class<DM>(rf + __builtin_amdgcn_readfirstlane(ns.rbeg[k]) * DM,
+                       __builtin_amdgcn_readfirstlane(ns.rcnt[k]), A.t_sample, tlo, thi, dd, lane,
+                       all, none);
+        if (all) {
+          ++near;
+          if (first < 0) first = k;
+        } else if (!none) {
+          mixed = true;
+        }
+      }
+      if (near < 2) {
+        if (mixed) return false;
+        if (near == 1) lab = first;
+      }
+    }
+  }
+  const uint32_t cnt0 = lane == 0 ? (uint32_t)nval : 0u;  // counts added once per tile
+  if (write_labels) {
+#pragma unroll
+    for (int i = 0; i < S; ++i)
+      if (base + i < s_hi) A.labels[base + i] = (int8_t)lab;
+  }
+  if (lab == -2) nex += cnt0;
+  const uint64_t m_ia = __ballot(in_all) & vm, m_in = __ballot(in_none) & vm;
+#pragma unroll
+  for (int k = 0; k < KC; ++k) {
+    if (k >= cnt) continue;
+    if (k == lab) {
+      nasg[k] += cnt0;
+      float mid[DM];
+      float lm = 0.f, um = 0.f;
+#pragma unroll
+      for (int a = 0; a < DM; ++a) {
+        amin[k][a] = fminf(amin[k][a], tlo[a]);
+        amax[k][a] = fmaxf(amax[k][a], thi[a]);
+        mid[a] = 0.5f * (bx[k * 2 * DM + 2 * a] + bx[k * 2 * DM + 2 * a + 1]);
+        if (a < dd) {
+          // least and greatest distance to the midpoint over the tile
+          const float g = fmaxf(fmaxf(mid[a] - thi[a], tlo[a] - mid[a]), 0.f);
+          const float u = fmaxf(thi[a] - mid[a], mid[a] - tlo[a]);
+          lm = (a == 0) ? g * g : __builtin_fmaf(g, g, lm);
+          um = (a == 0) ? u * u : __builtin_fmaf(u, u, um);
+        }
+      }
+      // an earlier tile of this label holds a sample farther from the
+      // midpoint than any sample of this one: the key cannot change
+      if (!(um < fw[k])) {
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+          if (base + i >= s_hi) continue;
+          float dm = 0.f;
+#pragma unroll
+          for (int a = 0; a < DM; ++a) {
+            if (a < dd) {
+              const float w = xs[i][a] - mid[a];
+              dm = (a == 0) ? w * w : __builtin_fmaf(w, w, dm);
+            }
+          }
+          const uint64_t key = kcd::key_max(dm, (uint32_t)(base + i));
+          far[k] = key > far[k] ? key : far[k];
+        }
+      }
+      fw[k] = fmaxf(fw[k], lm);
+    }
+    // S_+^k: inside box k and within the ball of every ref of box k
+    const uint64_t bit = 1ull << k;
+    if (m_in & bit) continue;
+    const int rb = __builtin_amdgcn_readfirstlane(ns.rbeg[k]);
+    const int rc = REFS ? __builtin_amdgcn_readfirstlane(ns.rcnt[k]) : 0;
+    bool ball_all = true, ball_none = false;
+    if (REFS && rc > 0) refs_class<DM>(rf + rb * DM, rc, A.t_ball, tlo, thi, dd, lane, ball_all, ball_none);
+    if (ball_none) continue;
+    if ((m_ia & bit) && ball_all) {
+      nin[k] += cnt0;
+#pragma unroll
+      for (int a = 0; a < DM; ++a) {
+        bmin[k][a] = fminf(bmin[k][a], tlo[a]);
+        bmax[k][a] = fmaxf(bmax[k][a], thi[a]);
+      }
+      continue;
+    }
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+      bool in = base + i < s_hi;
+#pragma unroll
+      for (int a = 0; a < DM; ++a)
+        if (a < dd)
+          in = in && (bx[k * 2 * DM + 2 * a] <= xs[i][a]) && (xs[i][a] <= bx[k * 2 * DM + 2 * a + 1]);
+      if (REFS && in && rc > 0)
+        in = all_refs_within(xs[i], rbx + k * 2 * DM, rf + rb * DM, rc, A.t_ball, dd, DM);
+      if (in) {
+        ++nin[k];
+#pragma unroll
+        for (int a = 0; a < DM; ++a) {
+          bmin[k][a] = fminf(bmin[k][a], xs[i][a]);
+          bmax[k][a] = fmaxf(bmax[k][a], xs[i][a]);
+        }
+      }
+    }
+  }
+  return true;
+}
+
 // D: attribute count (0 = any, up to 16); KC: boxes per chunk held in
 // registers; S: samples per lane per tile; NG: nodes per workgroup; REFS: the
 // batch carries refs (without refs none of that code is compiled in); MINW:
 // wavefronts per SIMD the register allocation must allow (0 = compiler's
-// choice).
-template <int D, int KC, int S, int NG, bool REFS, int MINW>
+// choice); TSKIP: wavefront tiles that the bounding box of their samples
+// settles skip the per-sample tests (single-chunk launches only).
+template <int D, int KC, int S, int NG, bool REFS, int MINW, bool TSKIP>
 __global__ __launch_bounds__(WG, MINW > 0 ? MINW : 1) void k_tighten(TightenArgs A) {
   constexpr int DM = D ? D : 16;
+  constexpr int SC = S < 4 ? S : 4;  // samples per chunk of the per-sample path
   const int dd = D ? D : A.d;
   extern __shared__ float sm[];  // per node slot: boxes [k_max][2DM], refs' boxes, refs
   __shared__ NodeSlot s_node[NG];
@@ -229,6 +430,7 @@ __global__ __launch_bounds__(WG, MINW > 0 ? MINW : 1) void k_tighten(TightenArgs
   float bmin[NG][KC][DM], bmax[NG][KC][DM], amin[NG][KC][DM], amax[NG][KC][DM];
   uint32_t nin[NG][KC], nasg[NG][KC];
   uint64_t far[NG][KC];
+  float fw[NG][KC];  // tile decisions: at most the farthest folded distance to the midpoint
   uint32_t nex[NG];
 #pragma unroll
   for (int jn = 0; jn < NG; ++jn) {
@@ -238,6 +440,7 @@ __global__ __launch_bounds__(WG, MINW > 0 ? MINW : 1) void k_tighten(TightenArgs
       nin[jn][kk] = 0;
       nasg[jn][kk] = 0;
       far[jn][kk] = 0;
+      fw[jn][kk] = -1.f;
 #pragma unroll
       for (int a = 0; a < DM; ++a) {
         bmin[jn][kk][a] = INFINITY;
@@ -258,19 +461,30 @@ __global__ __launch_bounds__(WG, MINW > 0 ? MINW : 1) void k_tighten(TightenArgs
 
   const int64_t s_lo = (int64_t)split * A.span;
   const int64_t s_hi = min(A.n, s_lo + A.span);
-  for (int64_t base = s_lo + (int64_t)tid * S; base < s_hi; base += (int64_t)WG * S) {
+  const int wave = tid >> 6;
+  // With tile decisions every lane runs the same number of tiles (the last
+  // tile of a split may hold samples past its end, which take no part), so
+  // that the wavefront decisions see whole wavefronts; without, a lane stops
+  // after its last sample.
+  const int64_t lane_off = (int64_t)tid * S;
+  for (int64_t base = s_lo + lane_off; (TSKIP ? base - lane_off : base) < s_hi;
+       base += (int64_t)WG * S) {
+    const int64_t tb = base - lane_off;
     float xs[S][DM];
     const bool full = base + S <= s_hi;
 #pragma unroll
     for (int a = 0; a < DM; ++a) {
       if (a < dd) {
         const float *p = A.x + (int64_t)a * A.ld + base;
-        if (full && S == 4) {
-          const float4 v = *reinterpret_cast<const float4 *>(p);
-          xs[0][a] = v.x;
-          xs[1 % S][a] = v.y;
-          xs[2 % S][a] = v.z;
-          xs[3 % S][a] = v.w;
+        if (full && S % 4 == 0) {
+#pragma unroll
+          for (int q = 0; q < S / 4; ++q) {
+            const float4 v = reinterpret_cast<const float4 *>(p)[q];
+            xs[(4 * q) % S][a] = v.x;
+            xs[(4 * q + 1) % S][a] = v.y;
+            xs[(4 * q + 2) % S][a] = v.z;
+            xs[(4 * q + 3) % S][a] = v.w;
+          }
         } else if (full && S == 2) {
           const float2 v = *reinterpret_cast<const float2 *>(p);
           xs[0][a] = v.x;
@@ -284,164 +498,211 @@ __global__ __launch_bounds__(WG, MINW > 0 ? MINW : 1) void k_tighten(TightenArgs
         for (int i = 0; i < S; ++i) xs[i][a] = 0.f;
       }
     }
+    // Wavefront tile: the 64 * S consecutive samples of this wavefront, their
+    // count and bounding box (uniform across the wavefront).
+    int nval = 0;
+    float tlo[DM], thi[DM];
+    if constexpr (TSKIP) {
+      const int64_t wb = tb + (int64_t)wave * 64 * S;
+      const int64_t left = s_hi - wb;
+      nval = left <= 0 ? 0 : (left >= 64 * S ? 64 * S : (int)left);
+#pragma unroll
+      for (int a = 0; a < DM; ++a) {
+        float l = INFINITY, h = -INFINITY;
+        if (a < dd) {
+#pragma unroll
+          for (int i = 0; i < S; ++i)
+            if (base + i < s_hi) {
+              l = fminf(l, xs[i][a]);
+              h = fmaxf(h, xs[i][a]);
+            }
+        }
+        tlo[a] = __int_as_float(__builtin_amdgcn_readfirstlane(
+            __float_as_int(kcd::fdec(kcd::wave_min_u32(kcd::ford(l))))));
+        thi[a] = __int_as_float(__builtin_amdgcn_readfirstlane(
+            __float_as_int(kcd::fdec(kcd::wave_max_u32(kcd::ford(h))))));
+      }
+    }
 
 #pragma unroll
     for (int jn = 0; jn < NG; ++jn) {
       if (m0 + jn >= A.n_nodes) break;  // workgroup-uniform
-      const float *bx = sm + jn * A.node_floats;
-      const float *rbx = bx + box_floats;
-      const float *rf = rbx + box_floats;
-      const int cnt = cnt_u[jn];
-      // Center-based assignment (Lemma 1), box-major: each box's bounds are
-      // read from LDS once for the lane's S samples. In the single-chunk case
-      // the same distances record which boxes hold each sample.
-      int n_out[S], keep[S], label[S];
-      uint32_t inm[S];
-#pragma unroll
-      for (int i = 0; i < S; ++i) {
-        n_out[i] = 0;
-        keep[i] = -1;
-        inm[i] = 0;
+      bool done = false;
+      if constexpr (TSKIP) {
+        if (nval == 0) {
+          done = true;  // no sample of this wavefront lies in the split
+        } else {
+          const float *bx = sm + jn * A.node_floats;
+          const float *rbx = bx + box_floats;
+          const float *rf = rbx + box_floats;
+          const int cnt = cnt_u[jn];
+          done = tile_node<D, KC, S, REFS>(A, xs, base, s_hi, nval, tlo, thi, bx, rbx, rf,
+                                           s_node[jn], cnt, allref[jn], lane, write_labels,
+                                           nex[jn], nin[jn], nasg[jn], far[jn], fw[jn], bmin[jn],
+                                           bmax[jn], amin[jn], amax[jn]);
+        }
       }
-      if (single) {
+      if (!done) {
+        // per-sample path, in chunks of SC samples of the lane
 #pragma unroll
-        for (int k = 0; k < KC; ++k) {
-          if (k < cnt) {
-            float lo[DM], hi[DM];
+        for (int i0 = 0; i0 < S; i0 += SC) {
+          const float *bx = sm + jn * A.node_floats;
+          const float *rbx = bx + box_floats;
+          const float *rf = rbx + box_floats;
+          const int cnt = cnt_u[jn];
+          // Center-based assignment (Lemma 1), box-major: each box's bounds are
+          // read from LDS once for the lane's SC samples. In the single-chunk case
+          // the same distances record which boxes hold each sample.
+          int n_out[SC], keep[SC], label[SC];
+          uint32_t inm[SC];
 #pragma unroll
-            for (int a = 0; a < DM; ++a) {
-              lo[a] = bx[k * 2 * DM + 2 * a];
-              hi[a] = bx[k * 2 * DM + 2 * a + 1];
-            }
+          for (int i = 0; i < SC; ++i) {
+            n_out[i] = 0;
+            keep[i] = -1;
+            inm[i] = 0;
+          }
+          if (single) {
 #pragma unroll
-            for (int i = 0; i < S; ++i) {
-              float acc = 0.f;
-              bool in = true;
+            for (int k = 0; k < KC; ++k) {
+              if (k < cnt) {
+                float lo[DM], hi[DM];
 #pragma unroll
-              for (int a = 0; a < DM; ++a) {
-                if (a < dd) {
-                  const float c = kcd::med3(lo[a], xs[i][a], hi[a]);
-                  in = in && (c == xs[i][a]);
-                  const float t = xs[i][a] - c;
-                  acc = (a == 0) ? t * t : __builtin_fmaf(t, t, acc);
+                for (int a = 0; a < DM; ++a) {
+                  lo[a] = bx[k * 2 * DM + 2 * a];
+                  hi[a] = bx[k * 2 * DM + 2 * a + 1];
+                }
+#pragma unroll
+                for (int i = 0; i < SC; ++i) {
+                  float acc = 0.f;
+                  bool in = true;
+#pragma unroll
+                  for (int a = 0; a < DM; ++a) {
+                    if (a < dd) {
+                      const float c = kcd::med3(lo[a], xs[i0 + i][a], hi[a]);
+                      in = in && (c == xs[i0 + i][a]);
+                      const float t = xs[i0 + i][a] - c;
+                      acc = (a == 0) ? t * t : __builtin_fmaf(t, t, acc);
+                    }
+                  }
+                  const bool out = acc > A.t_center;
+                  n_out[i] += out;
+                  keep[i] = out ? keep[i] : k;
+                  inm[i] |= (uint32_t)in << k;
                 }
               }
-              const bool out = acc > A.t_center;
-              n_out[i] += out;
-              keep[i] = out ? keep[i] : k;
-              inm[i] |= (uint32_t)in << k;
             }
-          }
-        }
-      } else {
-        for (int k = 0; k < cnt; ++k) {
-          float lo[DM], hi[DM];
+          } else {
+            for (int k = 0; k < cnt; ++k) {
+              float lo[DM], hi[DM];
 #pragma unroll
-          for (int a = 0; a < DM; ++a) {
-            lo[a] = bx[k * 2 * DM + 2 * a];
-            hi[a] = bx[k * 2 * DM + 2 * a + 1];
-          }
+              for (int a = 0; a < DM; ++a) {
+                lo[a] = bx[k * 2 * DM + 2 * a];
+                hi[a] = bx[k * 2 * DM + 2 * a + 1];
+              }
 #pragma unroll
-          for (int i = 0; i < S; ++i) {
-            float acc = 0.f;
+              for (int i = 0; i < SC; ++i) {
+                float acc = 0.f;
 #pragma unroll
-            for (int a = 0; a < DM; ++a) {
-              if (a < dd) {
-                const float t = xs[i][a] - kcd::med3(lo[a], xs[i][a], hi[a]);
-                acc = (a == 0) ? t * t : __builtin_fmaf(t, t, acc);
+                for (int a = 0; a < DM; ++a) {
+                  if (a < dd) {
+                    const float t = xs[i0 + i][a] - kcd::med3(lo[a], xs[i0 + i][a], hi[a]);
+                    acc = (a == 0) ? t * t : __builtin_fmaf(t, t, acc);
+                  }
+                }
+                const bool out = acc > A.t_center;
+                n_out[i] += out;
+                keep[i] = out ? keep[i] : k;
               }
             }
-            const bool out = acc > A.t_center;
-            n_out[i] += out;
-            keep[i] = out ? keep[i] : k;
+#pragma unroll
+            for (int kk = 0; kk < KC; ++kk) {
+              const int k = c0 + kk;
+              if (k < cnt) {
+#pragma unroll
+                for (int i = 0; i < SC; ++i) {
+                  bool in = true;
+#pragma unroll
+                  for (int a = 0; a < DM; ++a)
+                    if (a < dd)
+                      in = in && (bx[k * 2 * DM + 2 * a] <= xs[i0 + i][a]) &&
+                           (xs[i0 + i][a] <= bx[k * 2 * DM + 2 * a + 1]);
+                  inm[i] |= (uint32_t)in << kk;
+                }
+              }
+            }
           }
-        }
+
 #pragma unroll
-        for (int kk = 0; kk < KC; ++kk) {
-          const int k = c0 + kk;
-          if (k < cnt) {
+          for (int i = 0; i < SC; ++i) {
+            const float *xv = xs[i0 + i];
+            int lab = n_out[i] == cnt ? -2 : (n_out[i] == cnt - 1 ? keep[i] : -1);
+            if (base + i0 + i >= s_hi) {  // past the end: no contribution
+              lab = -3;
+              inm[i] = 0;
+            }
+            // Sample-based assignment (Lemma 2), only for unassigned samples:
+            // cluster k is excluded once one of its refs is farther than 4 alpha;
+            // the scan stops when two clusters remain possible.
+            if (REFS && lab == -1 && allref[jn]) {
+              int n_near = 0, rest_k = -1;
+              for (int k = 0; k < cnt && n_near < 2; ++k) {
+                const int rb = __builtin_amdgcn_readfirstlane(s_node[jn].rbeg[k]);
+                const int rc = __builtin_amdgcn_readfirstlane(s_node[jn].rcnt[k]);
+                if (all_refs_within(xv, rbx + k * 2 * DM, rf + rb * DM, rc, A.t_sample, dd, DM)) {
+                  ++n_near;
+                  rest_k = k;
+                }
+              }
+              if (n_near == 1) lab = rest_k;
+            }
+            if (write_labels && base + i0 + i < s_hi) A.labels[base + i0 + i] = (int8_t)lab;
+            nex[jn] += (lab == -2);
+            label[i] = lab;
+          }
+
+          // Running aggregates of the chunk's boxes, box-major.
 #pragma unroll
-            for (int i = 0; i < S; ++i) {
-              bool in = true;
+          for (int kk = 0; kk < KC; ++kk) {
+            const int k = c0 + kk;
+            if (k < cnt) {
+              float mid[DM];
 #pragma unroll
               for (int a = 0; a < DM; ++a)
-                if (a < dd)
-                  in = in && (bx[k * 2 * DM + 2 * a] <= xs[i][a]) &&
-                       (xs[i][a] <= bx[k * 2 * DM + 2 * a + 1]);
-              inm[i] |= (uint32_t)in << kk;
-            }
-          }
-        }
-      }
-
+                mid[a] = 0.5f * (bx[k * 2 * DM + 2 * a] + bx[k * 2 * DM + 2 * a + 1]);
+              const int rb = __builtin_amdgcn_readfirstlane(s_node[jn].rbeg[k]);
+              const int rc = __builtin_amdgcn_readfirstlane(s_node[jn].rcnt[k]);
 #pragma unroll
-      for (int i = 0; i < S; ++i) {
-        const float *xv = xs[i];
-        int lab = n_out[i] == cnt ? -2 : (n_out[i] == cnt - 1 ? keep[i] : -1);
-        if (base + i >= s_hi) {  // past the end: no contribution
-          lab = -3;
-          inm[i] = 0;
-        }
-        // Sample-based assignment (Lemma 2), only for unassigned samples:
-        // cluster k is excluded once one of its refs is farther than 4 alpha;
-        // the scan stops when two clusters remain possible.
-        if (REFS && lab == -1 && allref[jn]) {
-          int n_near = 0, rest_k = -1;
-          for (int k = 0; k < cnt && n_near < 2; ++k) {
-            const int rb = __builtin_amdgcn_readfirstlane(s_node[jn].rbeg[k]);
-            const int rc = __builtin_amdgcn_readfirstlane(s_node[jn].rcnt[k]);
-            if (all_refs_within(xv, rbx + k * 2 * DM, rf + rb * DM, rc, A.t_sample, dd, DM)) {
-              ++n_near;
-              rest_k = k;
-            }
-          }
-          if (n_near == 1) lab = rest_k;
-        }
-        if (write_labels && base + i < s_hi) A.labels[base + i] = (int8_t)lab;
-        nex[jn] += (lab == -2);
-        label[i] = lab;
-      }
-
-      // Running aggregates of the chunk's boxes, box-major.
+              for (int i = 0; i < SC; ++i) {
+                const float *xv = xs[i0 + i];
+                if (label[i] == k) {
+                  ++nasg[jn][kk];
+                  float dm = 0.f;
 #pragma unroll
-      for (int kk = 0; kk < KC; ++kk) {
-        const int k = c0 + kk;
-        if (k < cnt) {
-          float mid[DM];
+                  for (int a = 0; a < DM; ++a) {
+                    amin[jn][kk][a] = fminf(amin[jn][kk][a], xv[a]);
+                    amax[jn][kk][a] = fmaxf(amax[jn][kk][a], xv[a]);
+                    const float w = xv[a] - mid[a];
+                    dm = (a == 0) ? w * w : __builtin_fmaf(w, w, dm);
+                  }
+                  const uint64_t key = kcd::key_max(dm, (uint32_t)(base + i0 + i));
+                  far[jn][kk] = key > far[jn][kk] ? key : far[jn][kk];
+                }
+                // S_+^k: inside box k and within the ball of every ref of box k.
+                bool in = (inm[i] >> (single ? k : kk)) & 1u;
+                if (REFS && in && rc > 0)
+                  in = all_refs_within(xv, rbx + k * 2 * DM, rf + rb * DM, rc, A.t_ball, dd, DM);
+                if (in) {
+                  ++nin[jn][kk];
 #pragma unroll
-          for (int a = 0; a < DM; ++a)
-            mid[a] = 0.5f * (bx[k * 2 * DM + 2 * a] + bx[k * 2 * DM + 2 * a + 1]);
-          const int rb = __builtin_amdgcn_readfirstlane(s_node[jn].rbeg[k]);
-          const int rc = __builtin_amdgcn_readfirstlane(s_node[jn].rcnt[k]);
-#pragma unroll
-          for (int i = 0; i < S; ++i) {
-            const float *xv = xs[i];
-            if (label[i] == k) {
-              ++nasg[jn][kk];
-              float dm = 0.f;
-#pragma unroll
-              for (int a = 0; a < DM; ++a) {
-                amin[jn][kk][a] = fminf(amin[jn][kk][a], xv[a]);
-                amax[jn][kk][a] = fmaxf(amax[jn][kk][a], xv[a]);
-                const float w = xv[a] - mid[a];
-                dm = (a == 0) ? w * w : __builtin_fmaf(w, w, dm);
-              }
-              const uint64_t key = kcd::key_max(dm, (uint32_t)(base + i));
-              far[jn][kk] = key > far[jn][kk] ? key : far[jn][kk];
-            }
-            // S_+^k: inside box k and within the ball of every ref of box k.
-            bool in = (inm[i] >> (single ? k : kk)) & 1u;
-            if (REFS && in && rc > 0)
-              in = all_refs_within(xv, rbx + k * 2 * DM, rf + rb * DM, rc, A.t_ball, dd, DM);
-            if (in) {
-              ++nin[jn][kk];
-#pragma unroll
-              for (int a = 0; a < DM; ++a) {
-                bmin[jn][kk][a] = fminf(bmin[jn][kk][a], xv[a]);
-                bmax[jn][kk][a] = fmaxf(bmax[jn][kk][a], xv[a]);
+                  for (int a = 0; a < DM; ++a) {
+                    bmin[jn][kk][a] = fminf(bmin[jn][kk][a], xv[a]);
+                    bmax[jn][kk][a] = fmaxf(bmax[jn][kk][a], xv[a]);
+                  }
+                }
               }
             }
           }
+
         }
       }
     }
@@ -497,9 +758,11 @@ __global__ __launch_bounds__(WG, MINW > 0 ? MINW : 1) void k_tighten(TightenArgs
 // Compiled variants per attribute count (the autotuner's table). For KC boxes
 // per chunk: the default tile (S = 4 samples per lane, 16-byte loads, up to 4
 // attributes; 2 beyond), the same held to a register budget of another
-// occupancy, half the samples per lane, and -- where the per-node registers
-// allow (D * KC <= 20, resp. 8) -- 2 and 4 nodes per workgroup. Chunked
-// launches (more boxes than KC) and generic attribute counts use NG = 1.
+// occupancy, half the samples per lane, 2 nodes per workgroup where the
+// per-node registers allow (D * KC <= 20); and with wavefront tiles settled
+// from their bounding box: 1, 2 and 4 times the default samples per lane, and
+// 2 nodes per workgroup with 1 or 2 times. Chunked launches (more boxes than
+// KC) and generic attribute counts use NG = 1 without tile decisions.
 namespace kct {
 
 constexpr int sdef(int D) { return D > 0 && D <= 4 ? 4 : 2; }
@@ -508,29 +771,40 @@ constexpr int sdef(int D) { return D > 0 && D <= 4 ? 4 : 2; }
 constexpr int mwdef(int D, int KC) { return D > 0 && D * KC <= 6 ? 6 : 0; }
 constexpr int mwalt(int D, int KC) { return mwdef(D, KC) == 4 ? 2 : 4; }
 
-template <int D, int KC, int S, int NG, int MW>
+template <int D, int KC, int S, int NG, int MW, bool SK>
 inline bool go(bool refs, const TightenArgs &A, int grid, size_t lds, hipStream_t st) {
   if (refs)
-    k_tighten<D, KC, S, NG, true, MW><<<grid, WG, lds, st>>>(A);
+    k_tighten<D, KC, S, NG, true, MW, SK><<<grid, WG, lds, st>>>(A);
   else
-    k_tighten<D, KC, S, NG, false, MW><<<grid, WG, lds, st>>>(A);
+    k_tighten<D, KC, S, NG, false, MW, SK><<<grid, WG, lds, st>>>(A);
   return true;
 }
 
 template <int D, int KC>
-inline bool launch_kc(int S, int NG, int minw, bool refs, const TightenArgs &A, int grid,
+inline bool launch_kc(int S, int NG, int minw, int skip, bool refs, const TightenArgs &A, int grid,
                       size_t lds, hipStream_t st) {
   constexpr int SD = sdef(D), MD = mwdef(D, KC), MA = mwalt(D, KC);
-  if (S == SD && NG == 1 && minw == MD) return go<D, KC, SD, 1, MD>(refs, A, grid, lds, st);
-  if (S == SD && NG == 1 && minw == MA) return go<D, KC, SD, 1, MA>(refs, A, grid, lds, st);
-  if (S == SD / 2 && NG == 1 && minw == MD) return go<D, KC, SD / 2, 1, MD>(refs, A, grid, lds, st);
-  if constexpr (D > 0 && D * KC <= 20) {
-    if (S == SD && NG == 2 && minw == 0) return go<D, KC, SD, 2, 0>(refs, A, grid, lds, st);
-    if (S == SD / 2 && NG == 2 && minw == 0) return go<D, KC, SD / 2, 2, 0>(refs, A, grid, lds, st);
-  }
-  if constexpr (D > 0 && D * KC <= 8) {
-    if (S == SD && NG == 4 && minw == 0) return go<D, KC, SD, 4, 0>(refs, A, grid, lds, st);
-    if (S == SD / 2 && NG == 4 && minw == 0) return go<D, KC, SD / 2, 4, 0>(refs, A, grid, lds, st);
+  if (!skip) {
+    if (S == SD && NG == 1 && minw == MD) return go<D, KC, SD, 1, MD, false>(refs, A, grid, lds, st);
+    if (S == SD && NG == 1 && minw == MA) return go<D, KC, SD, 1, MA, false>(refs, A, grid, lds, st);
+    if (S == SD / 2 && NG == 1 && minw == MD)
+      return go<D, KC, SD / 2, 1, MD, false>(refs, A, grid, lds, st);
+    if constexpr (D > 0 && D * KC <= 20) {
+      if (S == SD && NG == 2 && minw == 0) return go<D, KC, SD, 2, 0, false>(refs, A, grid, lds, st);
+    }
+  } else if constexpr (D > 0) {
+    // wavefront tiles (64 S samples) settled from their bounding box
+    if (NG == 1 && minw == 0) {
+      if (S == SD) return go<D, KC, SD, 1, 0, true>(refs, A, grid, lds, st);
+      if (S == 2 * SD) return go<D, KC, 2 * SD, 1, 0, true>(refs, A, grid, lds, st);
+      if (S == 4 * SD) return go<D, KC, 4 * SD, 1, 0, true>(refs, A, grid, lds, st);
+    }
+    if constexpr (D * KC <= 20) {
+      if (NG == 2 && minw == 0) {
+        if (S == SD) return go<D, KC, SD, 2, 0, true>(refs, A, grid, lds, st);
+        if (S == 2 * SD) return go<D, KC, 2 * SD, 2, 0, true>(refs, A, grid, lds, st);
+      }
+    }
   }
   return false;
 }
@@ -540,27 +814,27 @@ inline bool launch_kc(int S, int NG, int minw, bool refs, const TightenArgs &A, 
 // Dispatch of one translation unit: DV_ attributes (0 = generic, up to 16).
 #define KC_TIGHTEN_DISPATCH(NAME)                                                        \
   namespace kct {                                                                       \
-  bool NAME(int kc, int S, int NG, int minw, bool refs, const TightenArgs &A, int grid, \
-            size_t lds, hipStream_t st) {                                               \
+  bool NAME(int kc, int S, int NG, int minw, int skip, bool refs, const TightenArgs &A,   \
+            int grid, size_t lds, hipStream_t st) {                                     \
     switch (kc) {                                                                       \
-      case 1: return launch_kc<DV_, 1>(S, NG, minw, refs, A, grid, lds, st);            \
-      case 2: return launch_kc<DV_, 2>(S, NG, minw, refs, A, grid, lds, st);            \
-      case 3: return launch_kc<DV_, 3>(S, NG, minw, refs, A, grid, lds, st);            \
-      case 4: return launch_kc<DV_, 4>(S, NG, minw, refs, A, grid, lds, st);            \
-      case 5: return launch_kc<DV_, 5>(S, NG, minw, refs, A, grid, lds, st);            \
-      case 6: return launch_kc<DV_, 6>(S, NG, minw, refs, A, grid, lds, st);            \
-      case 8: return launch_kc<DV_, 8>(S, NG, minw, refs, A, grid, lds, st);            \
+      case 1: return launch_kc<DV_, 1>(S, NG, minw, skip, refs, A, grid, lds, st);      \
+      case 2: return launch_kc<DV_, 2>(S, NG, minw, skip, refs, A, grid, lds, st);      \
+      case 3: return launch_kc<DV_, 3>(S, NG, minw, skip, refs, A, grid, lds, st);      \
+      case 4: return launch_kc<DV_, 4>(S, NG, minw, skip, refs, A, grid, lds, st);      \
+      case 5: return launch_kc<DV_, 5>(S, NG, minw, skip, refs, A, grid, lds, st);      \
+      case 6: return launch_kc<DV_, 6>(S, NG, minw, skip, refs, A, grid, lds, st);      \
+      case 8: return launch_kc<DV_, 8>(S, NG, minw, skip, refs, A, grid, lds, st);      \
       default: return false;                                                            \
     }                                                                                   \
   }                                                                                     \
   }
 #define KC_TIGHTEN_DISPATCH_GENERIC(NAME)                                                \
   namespace kct {                                                                       \
-  bool NAME(int kc, int S, int NG, int minw, bool refs, const TightenArgs &A, int grid, \
-            size_t lds, hipStream_t st) {                                               \
+  bool NAME(int kc, int S, int NG, int minw, int skip, bool refs, const TightenArgs &A,   \
+            int grid, size_t lds, hipStream_t st) {                                     \
     switch (kc) {                                                                       \
-      case 1: return launch_kc<0, 1>(S, NG, minw, refs, A, grid, lds, st);              \
-      case 2: return launch_kc<0, 2>(S, NG, minw, refs, A, grid, lds, st);              \
+      case 1: return launch_kc<0, 1>(S, NG, minw, skip, refs, A, grid, lds, st);        \
+      case 2: return launch_kc<0, 2>(S, NG, minw, skip, refs, A, grid, lds, st);        \
       default: return false;                                                            \
     }                                                                                   \
   }                                                                                     \

@@ -187,8 +187,16 @@ def shifted_geomean(ts, shift=1.0):
     return math.exp(sum(math.log(t + shift) for t in ts) / len(ts)) - shift
 
 
-def evaluate(seeds, n, k, wb, time_limit, batch=64, node_sr=0):
+def evaluate(seeds, n, k, wb, time_limit, batch=64, node_sr=0, autotune=False):
     rows = []
+    if autotune:
+        # fill the handle's tile table on the first instance (untimed) so that
+        # no tile sweep runs inside a timed solve
+        x, kk = datagen.learned_instance_device(seeds[0], n, k=k)
+        for rule in (0, 1):
+            api.solve(x, n, kk, batch=batch, i_sr=2, time_limit_s=min(time_limit, 5.0),
+                      branching=rule, mlp_w=wb if rule else None, node_sr=node_sr, autotune=True)
+        del x
     for seed in seeds:
         x, kk = datagen.learned_instance_device(seed, n, k=k)
         torch.cuda.synchronize()
@@ -196,7 +204,8 @@ def evaluate(seeds, n, k, wb, time_limit, batch=64, node_sr=0):
         for rule in ("plain", "learned"):
             r = api.solve(x, n, kk, batch=batch, i_sr=2, time_limit_s=time_limit,
                           branching=1 if rule == "learned" else 0,
-                          mlp_w=wb if rule == "learned" else None, node_sr=node_sr)
+                          mlp_w=wb if rule == "learned" else None, node_sr=node_sr,
+                          autotune=autotune)
             res[rule] = dict(seconds=r["seconds"], nodes=r["nodes"], gap=r["gap"],
                              solved=r["status"] == 0, obj=r["obj"], lb=r["lb"])
         rows.append(dict(seed=seed, k=kk, n=n, **res))
@@ -237,6 +246,8 @@ def main(argv=None):
     ap.add_argument("--report", default=None)
     ap.add_argument("--node-sr", type=int, default=0,
                     help="one-node sample reductions for nodes over at least this many samples")
+    ap.add_argument("--autotune", action="store_true",
+                    help="tile sweeps (in an untimed warm-up on the first instance)")
     a = ap.parse_args(argv)
     torch.cuda.set_device(0)
     report = {}
@@ -258,10 +269,10 @@ def main(argv=None):
     else:
         wb, meta = load(a.weights)
     lo, hi = (int(v) for v in a.eval_seeds.split(":"))
-    rows, summ = evaluate(range(lo, hi), a.eval_n, a.eval_k or None, wb, a.time_limit,
-                          node_sr=a.node_sr)
+    rows, summ = evaluate(list(range(lo, hi)), a.eval_n, a.eval_k or None, wb, a.time_limit,
+                          node_sr=a.node_sr, autotune=a.autotune)
     report["eval"] = dict(rows=rows, summary=summ, n=a.eval_n, k=a.eval_k or "U{4..8}",
-                          time_limit=a.time_limit, node_sr=a.node_sr)
+                          time_limit=a.time_limit, node_sr=a.node_sr, autotune=a.autotune)
     log("[eval] summary " + json.dumps(summ))
     if a.report:
         with open(a.report, "w") as f:

@@ -608,11 +608,13 @@ def _tighten_tiles(d, k):
     sd = 4 if 0 < D <= 4 else 2
     md = 6 if D > 0 and D * kc <= 6 else 0
     ma = 2 if md == 4 else 4
-    tiles = [(sd, 1, md), (sd, 1, ma), (sd // 2, 1, md)]
+    tiles = [(sd, 1, md, 0), (sd, 1, ma, 0), (sd // 2, 1, md, 0)]
     if single and D > 0 and D * kc <= 20:
-        tiles += [(sd, 2, 0), (sd // 2, 2, 0)]
-    if single and D > 0 and D * kc <= 8:
-        tiles += [(sd, 4, 0), (sd // 2, 4, 0)]
+        tiles.append((sd, 2, 0, 0))
+    if single and D > 0:  # wavefront tiles settled from their bounding box
+        tiles += [(m * sd, 1, 0, 1) for m in (1, 2, 4)]
+        if D * kc <= 20:
+            tiles += [(m * sd, 2, 0, 1) for m in (1, 2)]
     return tiles
 
 
@@ -634,13 +636,13 @@ def test_tighten_every_tile_matches_default(kc, tmp_path, seed, n, d, k, nn, wit
     bn = int(np.log2(nn)) if nn > 1 else 0
     bs = int(np.floor(np.log2(n))) // 2
     key = f"t_d{d}_k{k}_nn{bn}_n{bs}_r{int(bool(with_refs))}"
-    for S, NG, mw in _tighten_tiles(d, k):
-        path = tmp_path / f"tune_{S}_{NG}_{mw}.txt"
-        path.write_text(f"{key} {S} {NG} {mw}\n")
+    for S, NG, mw, skip in _tighten_tiles(d, k):
+        path = tmp_path / f"tune_{S}_{NG}_{mw}_{skip}.txt"
+        path.write_text(f"{key} {S} {NG} {mw} {skip}\n")
         h = kc.Handle(0, str(path))
         out = kc.tighten(*args, **kw, h=h)
         for name in keys:
-            assert np.array_equal(out[name].cpu().numpy(), ref_out[name]), (S, NG, mw, name)
+            assert np.array_equal(out[name].cpu().numpy(), ref_out[name]), (S, NG, mw, skip, name)
         h.close()
     h = kc.Handle(0)
     kc.autotune_tighten(*args, **kw, h=h)
@@ -648,3 +650,66 @@ def test_tighten_every_tile_matches_default(kc, tmp_path, seed, n, d, k, nn, wit
     for name in keys:
         assert np.array_equal(out[name].cpu().numpy(), ref_out[name]), name
     h.close()
+
+
+_LB_TILES = [(8, 1), (4, 1), (2, 1), (4, 2), (4, 4), (2, 4), (4, 8), (2, 8), (2, 16), (1, 16)]
+_LB_TS_TILES = [(8, 1), (4, 1), (4, 4), (4, 8), (2, 8)]
+_CAND_TILES = [(2, 8, 4), (2, 4, 4), (2, 1, 4), (4, 4, 4), (4, 2, 4), (2, 4, 8), (2, 2, 8), (2, 1, 8),
+               (4, 2, 8), (1, 4, 8), (1, 2, 16), (1, 1, 16), (1, 1, 64)]
+_CAND_TS_TILES = [(2, 8, 4), (2, 4, 4), (4, 4, 4), (4, 2, 8), (2, 2, 8), (2, 4, 8)]
+_PT_TILES = [(4, 1), (2, 4), (2, 8)]
+
+
+def _bound_key(d, cand, nn, k, n):
+    kb = 4 if k <= 4 else 8 if k <= 8 else 16 if k <= 16 else 64
+    return f"d{d}_c{int(cand)}_nn{int(np.log2(nn)) if nn > 1 else 0}_k{kb}_n{int(np.floor(np.log2(n))) // 2}"
+
+
+@pytest.mark.parametrize("n,d,nn,k,ordered,seed", [(200_003, 2, 24, 3, True, 40), (150_000, 4, 17, 5, True, 41),
+                                                     (100_000, 3, 9, 10, False, 42), (80_000, 5, 6, 8, True, 43)])
+def test_bound_every_tile_matches_default(kc, tmp_path, n, d, nn, k, ordered, seed):
+    """Every lower-bound and candidate tile the autotuner can pick, with and
+    without wavefront tile decisions (read from a tune cache file), gives the
+    default tile's bounds, argmax and candidates bit for bit; likewise every
+    tile of the float32 objective."""
+    X = datagen.gaussian_mixture(n, d, 4, 0.08, seed)
+    if ordered:
+        X = np.ascontiguousarray(X[_morton(X)])
+    xd = kc.to_device_soa(X)
+    off, lo, hi = datagen.random_boxes(nn, k, d, seed, wmin=0.01, wmax=0.4)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    args = (xd, n, dev(off), dev(lo), dev(hi))
+    kc_box = 4 if k <= 4 else 8 if k <= 8 else 16 if k <= 16 else 64
+    ts = 1 <= d <= 8
+    for cand in (False, True):
+        ref = [t.cpu().numpy() for t in kc.lower_bound(*args, k_max=k, want_cand=cand) if t is not None]
+        if cand:
+            tiles = [(S, NG, 0) for S, NG, KC in _CAND_TILES if KC == kc_box]
+            tiles += [(S, NG, 1) for S, NG, KC in _CAND_TS_TILES if KC == kc_box and ts]
+        else:
+            tiles = [(S, NG, 0) for S, NG in _LB_TILES] + [(S, NG, 1) for S, NG in _LB_TS_TILES if ts]
+        key = _bound_key(d, cand, nn, k, n)
+        for S, NG, skip in tiles:
+            path = tmp_path / f"tune_b{int(cand)}_{S}_{NG}_{skip}.txt"
+            path.write_text(f"{key} {S} {NG} 8 {skip}\n")
+            h = kc.Handle(0, str(path))
+            got = [t.cpu().numpy() for t in kc.lower_bound(*args, k_max=k, want_cand=cand, h=h)
+                   if t is not None]
+            h.close()
+            for a, b in zip(ref, got):
+                assert np.array_equal(a, b), (cand, S, NG, skip)
+    # float32 objective of candidate sets (K centers each)
+    rng = np.random.default_rng(seed)
+    C = X[rng.integers(0, n, (nn, k))].astype(np.float32)
+    ref = [t.cpu().numpy() for t in kc.objective(xd, n, dev(C), precision=32)]
+    bn = int(np.log2(nn)) if nn > 1 else 0
+    okey = f"o_d{d}_ns{bn}_k{k}_n{int(np.floor(np.log2(n))) // 2}"
+    for S, NG in _PT_TILES:
+        for skip in (0, 1) if ts else (0,):
+            path = tmp_path / f"tune_o_{S}_{NG}_{skip}.txt"
+            path.write_text(f"{okey} {S} {NG} 8 {skip}\n")
+            h = kc.Handle(0, str(path))
+            got = [t.cpu().numpy() for t in kc.objective(xd, n, dev(C), precision=32, h=h)]
+            h.close()
+            for a, b in zip(ref, got):
+                assert np.array_equal(a, b), ("objective", S, NG, skip)
