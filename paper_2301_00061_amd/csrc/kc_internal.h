@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdint>
 #include <map>
 #include <new>
@@ -43,7 +44,7 @@ struct kc_handle {
     const float *x = nullptr;
     int64_t n = 0;
     void *scratch = nullptr;
-    size_t keep_bytes = 0, cnt_bytes = 0;
+    size_t keep_bytes = 0, cnt_bytes = 0, off_bytes = 0, bsum_bytes = 0;
   } red;
 };
 
@@ -76,12 +77,16 @@ kc_status kc_validate_refs(kc_handle *h, const kc_refs *r, const kc_nodes *m);
 // mode 0: lower bound (optionally with candidates), mode 1: float32 objective.
 // fixed_scratch (nullable): device memory of fixed_bytes for the per-split
 // partial keys instead of the handle's scratch; a launch that needs more
-// fails with KC_EINVAL and allocates nothing.
+// fails with KC_EINVAL and allocates nothing. cut (mode 1 only; +inf = off):
+// a set whose float32 objective exceeds cut may stop early and report the
+// value of some sample above the cut (a lower bound of its objective); sets
+// at or below the cut get their exact value.
 kc_status kc_launch_bound(kc_handle *h, const kc_points *pts, int mode, int n_nodes,
                           int n_boxes, int k_max, const int32_t *box_off, const float *lo,
                           const float *hi, float *val_raw, double *val_bound, int64_t *argmax,
                           int64_t *cand, const kc_tile &t, hipStream_t st,
-                          void *fixed_scratch = nullptr, size_t fixed_bytes = 0);
+                          void *fixed_scratch = nullptr, size_t fixed_bytes = 0,
+                          float cut = INFINITY);
 // Takes the device address of kc_lower_bound_noalloc's static scratch array
 // for the current device (kc_bound.hip); called by kc_create with h->device
 // current.

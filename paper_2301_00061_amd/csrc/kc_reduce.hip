@@ -29,6 +29,7 @@ struct FlagArgs {
   int n_refs, max_refs;
   float t_beta;   // alpha_s(M) < t_beta   => LB-redundant in M
   float t_alpha;  // dist > t_alpha        => UB-redundant with that ref
+  int lg_kp;      // tile decisions: 2^lg_kp >= k_max lanes per node
   uint8_t *keep;
   uint32_t *tile_cnt;
 };
@@ -84,29 +85,181 @@ __device__ __forceinline__ bool redundant_in_node(const FlagArgs &A, int m, cons
   return ub && (as < A.t_beta);
 }
 
-template <int D>
+// Tile decisions: nodes g0 .. g0 + 64/KP - 1 (KP = 2^lg lanes per node, at
+// least k_max) classified for a wavefront's tile of samples with bounding box
+// [tlo, thi], one (node, box) pair per lane. The bounds over the tile are the
+// per-sample operations in the same order on the tile's extreme coordinates;
+// float32 rounding is monotone, so a bound on the safe side of a threshold
+// gives every sample of the tile the same outcome. Bit (jn << lg) of
+// *keep_all: no sample of the tile is redundant in node g0 + jn; of *red_all:
+// every sample is (or the node does not exist).
+template <int DM>
+__device__ __forceinline__ void classify_nodes(const FlagArgs &A, int g0, int lg,
+                                               const float (&tlo)[DM], const float (&thi)[DM],
+                                               int dd, int lane, uint64_t &keep_all,
+                                               uint64_t &red_all) {
+  const int KP = 1 << lg;
+  const int jn = lane >> lg, k = lane & (KP - 1);
+  const int m = g0 + jn;
+  const bool node_ok = m < A.n_nodes;
+  float alo = INFINITY, ahi = INFINITY;
+  bool ub_all = true, ub_none = false;
+  if (node_ok) {
+    const int b0 = kcd::clampi(A.box_off[m], 0, A.n_boxes);
+    const int b1 = kcd::clampi(A.box_off[m + 1], b0, A.n_boxes);
+    const int cnt = min(b1 - b0, A.k_max);
+    if (k < cnt) {
+      const float *l = A.lo + (int64_t)(b0 + k) * dd;
+      const float *h = A.hi + (int64_t)(b0 + k) * dd;
+      float lacc = 0.f, hacc = 0.f;
+      bool in_all = true, in_none = false;
+#pragma unroll
+      for (int a = 0; a < DM; ++a) {
+        if (a < dd) {
+          const float la = l[a], ha = h[a];
+          // |x - la| and |x - ha| over the tile's range: x - c rounds
+          // monotonically in x, so the extremes sit at the range's ends
+          const float ul = fmaxf(fabsf(tlo[a] - la), fabsf(thi[a] - la));
+          const float uh = fmaxf(fabsf(tlo[a] - ha), fabsf(thi[a] - ha));
+          const float gl = fmaxf(fmaxf(tlo[a] - la, la - thi[a]), 0.f);
+          const float gh = fmaxf(fmaxf(tlo[a] - ha, ha - thi[a]), 0.f);
+          const float tu = fmaxf(ul, uh), tl = fmaxf(gl, gh);
+          lacc = (a == 0) ? tl * tl : __builtin_fmaf(tl, tl, lacc);
+          hacc = (a == 0) ? tu * tu : __builtin_fmaf(tu, tu, hacc);
+          in_all = in_all && la <= tlo[a] && thi[a] <= ha;
+          in_none = in_none || thi[a] < la || tlo[a] > ha;
+        }
+      }
+      alo = lacc;
+      ahi = hacc;
+      if (!in_none) {
+        // some ref farther than alpha from the whole tile / every ref within
+        // alpha of the whole tile
+        bool far_all = false, far_none = true;
+        if (A.ref_off) {
+          const int rb = kcd::clampi(A.ref_off[b0 + k], 0, A.n_refs);
+          const int re = kcd::clampi(A.ref_off[b0 + k + 1], rb, A.n_refs);
+          const int rc = min(re - rb, A.max_refs);
+          for (int r = 0; r < rc; ++r) {
+            const float *rr = A.ref + (int64_t)(rb + r) * dd;
+            float dn = 0.f, dx = 0.f;
+#pragma unroll
+            for (int a = 0; a < DM; ++a) {
+              if (a < dd) {
+                const float g = fmaxf(fmaxf(rr[a] - thi[a], tlo[a] - rr[a]), 0.f);
+                const float u = fmaxf(thi[a] - rr[a], rr[a] - tlo[a]);
+                dn = (a == 0) ? g * g : __builtin_fmaf(g, g, dn);
+                dx = (a == 0) ? u * u : __builtin_fmaf(u, u, dx);
+              }
+            }
+            far_all = far_all || dn > A.t_alpha;
+            far_none = far_none && !(dx > A.t_alpha);
+          }
+        }
+        ub_all = far_all;
+        ub_none = in_all && far_none;
+      }
+    }
+  }
+  // node-wide values: minimum over the node's lanes; AND / OR of the flags
+  for (int o = 1; o < KP; o <<= 1) {
+    alo = fminf(alo, __shfl_xor(alo, o));
+    ahi = fminf(ahi, __shfl_xor(ahi, o));
+  }
+  const uint64_t seg = KP >= 64 ? ~0ull : ((1ull << KP) - 1ull);
+  const uint64_t b_nall = __ballot(!ub_all), b_none = __ballot(ub_none);
+  const int sh = jn << lg;
+  const bool uba = ((b_nall >> sh) & seg) == 0, ubn = ((b_none >> sh) & seg) != 0;
+  keep_all = __ballot(k == 0 && node_ok && (!(alo < A.t_beta) || ubn));
+  red_all = __ballot(k == 0 && (!node_ok || (ahi < A.t_beta && uba)));
+}
+
+// Each lane holds PER consecutive samples, so a wavefront's tile is 64 * PER
+// consecutive samples (coherent when the samples are spatially ordered). A
+// sample is redundant when it is redundant in every open node; the node loop
+// stops once no lane's sample can still be. TS: tile decisions settle a node
+// for the whole tile where they can (the per-sample test runs only for the
+// nodes they leave open); the flags are the same either way.
+template <int D, bool TS>
 __global__ __launch_bounds__(WG) void k_reduce_flags(FlagArgs A) {
   constexpr int DM = D ? D : 16;
   const int dd = D ? D : A.d;
   __shared__ uint32_t s_cnt[WG / 64];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t base = (int64_t)blockIdx.x * TILE;
+  const int64_t s0 = (int64_t)blockIdx.x * TILE + (int64_t)tid * PER;
+  float xv[PER][DM];
+  bool valid[PER], red[PER];
+#pragma unroll
+  for (int a = 0; a < DM; ++a) {
+    const float *p = A.x + (int64_t)a * A.ld + s0;
+    if (a < dd && s0 + PER <= A.n && ((uintptr_t)p & 15) == 0) {
+      const float4 v = *reinterpret_cast<const float4 *>(p);
+      xv[0][a] = v.x;
+      xv[1][a] = v.y;
+      xv[2][a] = v.z;
+      xv[3][a] = v.w;
+    } else {
+#pragma unroll
+      for (int j = 0; j < PER; ++j) xv[j][a] = (a < dd && s0 + j < A.n) ? p[j] : 0.f;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    valid[j] = s0 + j < A.n;
+    red[j] = valid[j];  // redundant everywhere until a node shows otherwise
+  }
+  auto any_red = [&]() {
+    bool r = false;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) r = r || red[j];
+    return __ballot(r) != 0;
+  };
+  float tlo[DM], thi[DM];
+  if constexpr (TS) {
+#pragma unroll
+    for (int a = 0; a < DM; ++a) {
+      float l = INFINITY, h = -INFINITY;
+      if (a < dd) {
+#pragma unroll
+        for (int j = 0; j < PER; ++j)
+          if (valid[j]) {
+            l = fminf(l, xv[j][a]);
+            h = fmaxf(h, xv[j][a]);
+          }
+      }
+      tlo[a] = __int_as_float(__builtin_amdgcn_readfirstlane(
+          __float_as_int(kcd::fdec(kcd::wave_min_u32(kcd::ford(l))))));
+      thi[a] = __int_as_float(__builtin_amdgcn_readfirstlane(
+          __float_as_int(kcd::fdec(kcd::wave_max_u32(kcd::ford(h))))));
+    }
+  }
+  const int lg = A.lg_kp;
+  const int npg = TS ? (64 >> lg) : A.n_nodes;
+  for (int g0 = 0; g0 < A.n_nodes; g0 += npg) {
+    if (!any_red()) break;
+    uint64_t keep_all = 0, red_all = 0;
+    if constexpr (TS) {
+      classify_nodes<DM>(A, g0, lg, tlo, thi, dd, lane, keep_all, red_all);
+      if (keep_all) {  // some node keeps every sample of the tile
+#pragma unroll
+        for (int j = 0; j < PER; ++j) red[j] = false;
+        break;
+      }
+    }
+    const int g1 = min(A.n_nodes, g0 + npg);
+    for (int m = g0; m < g1; ++m) {
+      if (TS && ((red_all >> ((m - g0) << lg)) & 1ull)) continue;
+      if (!any_red()) break;
+#pragma unroll
+      for (int j = 0; j < PER; ++j)
+        if (red[j]) red[j] = redundant_in_node<D>(A, m, xv[j], dd);
+    }
+  }
   uint32_t kept = 0;
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
-    const int64_t s = base + (int64_t)j * WG + tid;
-    const bool valid = s < A.n;
-    float xv[DM];
-#pragma unroll
-    for (int a = 0; a < DM; ++a) xv[a] = (valid && a < dd) ? A.x[(int64_t)a * A.ld + s] : 0.f;
-    // redundant everywhere until a node shows otherwise
-    bool red = valid;
-    for (int m = 0; m < A.n_nodes; ++m) {
-      if (__ballot(red) == 0) break;
-      if (red) red = redundant_in_node<D>(A, m, xv, dd);
-    }
-    const bool keep = valid && !red;
-    if (valid) A.keep[s] = keep ? 1 : 0;
+    const bool keep = valid[j] && !red[j];
+    if (valid[j]) A.keep[s0 + j] = keep ? 1 : 0;
     kept += keep;
   }
   const uint32_t w = kcd::wave_sum_u32(kept);
@@ -119,7 +272,44 @@ __global__ __launch_bounds__(WG) void k_reduce_flags(FlagArgs A) {
   }
 }
 
-// One workgroup: exclusive scan of the tile counts; total into *n_out.
+// Tile offsets in two levels: k_scan_local scans SCAN_BLOCK tile counts per
+// workgroup (block-local exclusive offsets, at most 2^21, and the block's
+// total); k_reduce_scan then scans the block totals in one workgroup. A
+// tile's output position is its block's offset plus its local offset.
+constexpr int SCAN_PER = 8;
+constexpr int SCAN_BLOCK = WG * SCAN_PER;
+
+__global__ __launch_bounds__(WG) void k_scan_local(const uint32_t *cnt, int64_t n_tiles,
+                                                   uint32_t *off, uint32_t *bsum) {
+  __shared__ uint32_t s_w[WG / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t i0 = (int64_t)blockIdx.x * SCAN_BLOCK + (int64_t)tid * SCAN_PER;
+  uint32_t v[SCAN_PER], sum = 0;
+#pragma unroll
+  for (int j = 0; j < SCAN_PER; ++j) {
+    v[j] = i0 + j < n_tiles ? cnt[i0 + j] : 0u;
+    sum += v[j];
+  }
+  uint32_t x = sum;  // inclusive scan over the wavefront
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) s_w[wave] = x;
+  __syncthreads();
+  uint32_t wbase = 0;
+  for (int w = 0; w < wave; ++w) wbase += s_w[w];
+  uint32_t run = wbase + x - sum;
+#pragma unroll
+  for (int j = 0; j < SCAN_PER; ++j) {
+    if (i0 + j < n_tiles) off[i0 + j] = run;
+    run += v[j];
+  }
+  if (tid == WG - 1) bsum[blockIdx.x] = wbase + x;
+}
+
+// One workgroup: exclusive scan of the block totals; total into *n_out.
 __global__ __launch_bounds__(1024) void k_reduce_scan(const uint32_t *cnt, int64_t n_tiles,
                                                       int64_t *off, int64_t *n_out) {
   __shared__ int64_t s[1024];
@@ -148,7 +338,8 @@ __global__ __launch_bounds__(1024) void k_reduce_scan(const uint32_t *cnt, int64
 template <int D>
 __global__ __launch_bounds__(WG) void k_reduce_scatter(const float *x, int64_t n, int64_t ld,
                                                        int d, const uint32_t *idx_in,
-                                                       const uint8_t *keep, const int64_t *off,
+                                                       const uint8_t *keep, const uint32_t *off,
+                                                       const int64_t *boff,
                                                        float *x_out, uint32_t *idx_out,
                                                        int64_t ld_out) {
   constexpr int DM = D ? D : 16;
@@ -167,7 +358,7 @@ __global__ __launch_bounds__(WG) void k_reduce_scatter(const float *x, int64_t n
   }
   __syncthreads();
   const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
-  int64_t pos0 = off[blockIdx.x];
+  int64_t pos0 = boff[blockIdx.x / SCAN_BLOCK] + off[blockIdx.x];
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
     // samples are ordered (j, wave, lane) within the tile
@@ -187,11 +378,14 @@ __global__ __launch_bounds__(WG) void k_reduce_scatter(const float *x, int64_t n
 
 #define KCR_D(DV)                                                          \
   case DV:                                                                 \
-    if (flags)                                                             \
-      k_reduce_flags<DV><<<grid, WG, 0, st>>>(*FA);                        \
+    if (flags && skip)                                                     \
+      k_reduce_flags<DV, true><<<grid, WG, 0, st>>>(*FA);                  \
+    else if (flags)                                                        \
+      k_reduce_flags<DV, false><<<grid, WG, 0, st>>>(*FA);                 \
     else                                                                   \
       k_reduce_scatter<DV><<<grid, WG, 0, st>>>(SA.x, SA.n, SA.ld, SA.d, SA.idx_in, SA.keep, \
-                                                SA.off, SA.x_out, SA.idx_out, SA.ld_out);     \
+                                                SA.off, SA.boff, SA.x_out, SA.idx_out,        \
+                                                SA.ld_out);                                   \
     return KC_OK;
 
 struct ScatterArgs {
@@ -200,14 +394,15 @@ struct ScatterArgs {
   int d;
   const uint32_t *idx_in;
   const uint8_t *keep;
-  const int64_t *off;
+  const uint32_t *off;
+  const int64_t *boff;
   float *x_out;
   uint32_t *idx_out;
   int64_t ld_out;
 };
 
-static kc_status launch(int d, bool flags, const FlagArgs *FA, const ScatterArgs &SA, int64_t grid,
-                        hipStream_t st) {
+static kc_status launch(int d, bool flags, bool skip, const FlagArgs *FA, const ScatterArgs &SA,
+                        int64_t grid, hipStream_t st) {
   switch (d <= 8 ? d : 0) {
     KCR_D(1)
     KCR_D(2)
@@ -226,19 +421,35 @@ static kc_status launch(int d, bool flags, const FlagArgs *FA, const ScatterArgs
 
 using namespace kcr;
 
+// Tile decisions on unless the autotune table holds "r_d<d>" with skip 0
+// (tests compare the two paths).
+static bool reduce_tiles(kc_handle *h, int d) {
+  char key[32];
+  snprintf(key, sizeof key, "r_d%d", d);
+  const auto it = h->tune.find(std::string_view(key));
+  return it == h->tune.end() || it->second.skip != 0;
+}
+
 static kc_status count_impl(kc_handle *h, const kc_points *in, const kc_nodes *open,
                             const kc_refs *refs, double beta, double alpha, uint8_t *keep,
                             int64_t *n_out, hipStream_t st) {
   const int64_t n_tiles = (in->n + TILE - 1) / TILE;
+  const int64_t n_blocks = (n_tiles + SCAN_BLOCK - 1) / SCAN_BLOCK;
   const size_t keep_bytes = keep ? 0 : (((size_t)in->n + 255) & ~(size_t)255);
   const size_t cnt_bytes = (((size_t)n_tiles * 4) + 255) & ~(size_t)255;
-  const size_t off_bytes = (size_t)n_tiles * 8;
+  const size_t off_bytes = (((size_t)n_tiles * 4) + 255) & ~(size_t)255;
+  const size_t bsum_bytes = (((size_t)n_blocks * 4) + 255) & ~(size_t)255;
+  const size_t boff_bytes = (size_t)n_blocks * 8;
   void *scr = nullptr;
-  kc_status s = kc_get_scratch(h, keep_bytes + cnt_bytes + off_bytes, &scr);
+  kc_status s =
+      kc_get_scratch(h, keep_bytes + cnt_bytes + off_bytes + bsum_bytes + boff_bytes, &scr);
   if (s != KC_OK) return s;
   uint8_t *kf = keep ? keep : (uint8_t *)scr;
-  uint32_t *tcnt = (uint32_t *)((char *)scr + keep_bytes);
-  int64_t *toff = (int64_t *)((char *)scr + keep_bytes + cnt_bytes);
+  char *sp = (char *)scr + keep_bytes;
+  uint32_t *tcnt = (uint32_t *)sp;
+  uint32_t *toff = (uint32_t *)(sp + cnt_bytes);
+  uint32_t *bsum = (uint32_t *)(sp + cnt_bytes + off_bytes);
+  int64_t *boff = (int64_t *)(sp + cnt_bytes + off_bytes + bsum_bytes);
 
   FlagArgs A;
   A.x = in->x;
@@ -261,11 +472,17 @@ static kc_status count_impl(kc_handle *h, const kc_points *in, const kc_nodes *o
   A.tile_cnt = tcnt;
   ScatterArgs SA{};
   h->red.x = nullptr;
-  s = launch(in->d, true, &A, SA, n_tiles, st);
+  int lg = 0;
+  while ((1 << lg) < open->k_max && lg < 6) ++lg;
+  A.lg_kp = lg;
+  s = launch(in->d, true, reduce_tiles(h, in->d), &A, SA, n_tiles, st);
   if (s != KC_OK) return kc_fail(h, s, "reduce flags launch");
   s = kc_check_launch(h, "k_reduce_flags");
   if (s != KC_OK) return s;
-  k_reduce_scan<<<1, 1024, 0, st>>>(tcnt, n_tiles, toff, n_out);
+  k_scan_local<<<(unsigned)n_blocks, WG, 0, st>>>(tcnt, n_tiles, toff, bsum);
+  s = kc_check_launch(h, "k_scan_local");
+  if (s != KC_OK) return s;
+  k_reduce_scan<<<1, 1024, 0, st>>>(bsum, n_blocks, boff, n_out);
   s = kc_check_launch(h, "k_reduce_scan");
   if (s != KC_OK) return s;
   h->red.x = in->x;
@@ -273,6 +490,8 @@ static kc_status count_impl(kc_handle *h, const kc_points *in, const kc_nodes *o
   h->red.scratch = scr;
   h->red.keep_bytes = keep_bytes;
   h->red.cnt_bytes = cnt_bytes;
+  h->red.off_bytes = off_bytes;
+  h->red.bsum_bytes = bsum_bytes;
   return KC_OK;
 }
 
@@ -286,10 +505,12 @@ static kc_status compact_impl(kc_handle *h, const kc_points *in, const uint32_t 
   const int64_t n_tiles = (in->n + TILE - 1) / TILE;
   char *scr = (char *)h->red.scratch;
   const uint8_t *kf = keep ? keep : (const uint8_t *)scr;
-  const int64_t *toff = (const int64_t *)(scr + h->red.keep_bytes + h->red.cnt_bytes);
-  ScatterArgs SA{in->x, in->n, in->ld, in->d, idx_in, kf, toff, x_out, idx_out, ld_out};
+  const uint32_t *toff = (const uint32_t *)(scr + h->red.keep_bytes + h->red.cnt_bytes);
+  const int64_t *boff = (const int64_t *)(scr + h->red.keep_bytes + h->red.cnt_bytes +
+                                          h->red.off_bytes + h->red.bsum_bytes);
+  ScatterArgs SA{in->x, in->n, in->ld, in->d, idx_in, kf, toff, boff, x_out, idx_out, ld_out};
   h->red.x = nullptr;
-  kc_status s = launch(in->d, false, nullptr, SA, n_tiles, st);
+  kc_status s = launch(in->d, false, false, nullptr, SA, n_tiles, st);
   if (s != KC_OK) return kc_fail(h, s, "reduce scatter launch");
   return kc_check_launch(h, "k_reduce_scatter");
 }
