@@ -252,6 +252,10 @@ def main() -> int:
                          "(0 = off; default: the workload's setting)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="solve with the default tiles (no tile sweeps in the warm-up)")
+    ap.add_argument("--batch", type=int, default=None,
+                    help="nodes per pass (default: the workload's setting)")
+    ap.add_argument("--time-limit", type=float, default=None,
+                    help="seconds per solve (default: the workload's setting; 0 = none)")
     ap.add_argument("--verbose", action="store_true",
                     help="the solver's progress lines on stderr (nodes, incumbent, bound, time)")
     args = ap.parse_args()
@@ -276,8 +280,10 @@ def main() -> int:
     api.handle()
     n, k, d = W["n"], W["k"], W["d"]
     node_sr = args.node_sr if args.node_sr is not None else W.get("node_sr", 0)
-    opts = dict(batch=W["batch"], i_sr=W["i_sr"], max_nodes=W["passes"] * W["batch"] if W["passes"] else 0,
-                node_sr=node_sr, time_limit_s=W.get("time_limit", 0.0),
+    batch = args.batch or W["batch"]
+    tlim = args.time_limit if args.time_limit is not None else W.get("time_limit", 0.0)
+    opts = dict(batch=batch, i_sr=W["i_sr"], max_nodes=W["passes"] * batch if W["passes"] else 0,
+                node_sr=node_sr, time_limit_s=tlim,
                 autotune=not args.no_autotune, verbose=args.verbose)
 
     # one plain device copy of the points (known size: read and write
@@ -360,7 +366,7 @@ def main() -> int:
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "d": d, "k": k,
-                   "batch_nodes": W["batch"], "passes_per_step": W["passes"],
+                   "batch_nodes": batch, "passes_per_step": W["passes"], "time_limit_s": tlim,
                    "sample_reduction_every": W["i_sr"], "node_sr": node_sr,
                    "autotune": not args.no_autotune,
                    "node_sr_kept": r0["node_sr_kept"], "nodes_per_step": r0["nodes"],

@@ -131,12 +131,15 @@ kc_status kc_lower_bound(kc_handle *h, const kc_points *pts, const kc_nodes *nod
 /* kc_lower_bound for callers that cannot allocate device memory: code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
  * Same arguments, results, validation and stream semantics as kc_lower_bound
- * (same kernels and tiles), but the per-split partial results live in a
- * static device array of KC_NOALLOC_SCRATCH_BYTES per GPU, whose address the
+ * (same kernels and tiles), but the per-split partial results (and, for
+ * tiles with wavefront decisions, the per-node and per-box values the
+ * workgroups share) live in a static device array of KC_NOALLOC_SCRATCH_BYTES
+ * per GPU, whose address the
  * handle takes once per device in kc_create; the call makes no device or host
  * allocation and never synchronises. The caller still owns every input and
  * output buffer. A request whose partial results exceed the array (roughly
- * 8 bytes x (n_nodes + n_boxes with cand) x splits; at most about 2^19
+ * 8 bytes x (n_nodes + n_boxes with cand) x splits, plus 4 bytes per node
+ * and box for shared tile values; at most about 2^19
  * node+box slots in total) fails with KC_EINVAL and a message naming the
  * limit. Every call on one GPU shares that GPU's array: calls that overlap on
  * one GPU (several streams or host threads) race and give unspecified
@@ -153,6 +156,18 @@ kc_status kc_lower_bound_noalloc(kc_handle *h, const kc_points *pts, const kc_no
 kc_status kc_objective(kc_handle *h, const kc_points *pts, int32_t n_sets, int32_t k,
                        const float *centers, int32_t precision, double *obj,
                        int64_t *argmax, void *stream);
+
+/* The float32 objective of eq (12) as an upper-bound screen (Section 3.2:
+ * only a candidate set that improves the incumbent matters). Sets whose
+ * float32 value v is at most `cut` (host float) get exactly what
+ * kc_objective(precision = 32) gives; a set with v > cut may stop early and
+ * then reports the float32 value of some sample above cut (obj rounded up by
+ * the margin from that value, argmax that sample): a lower bound of its
+ * objective, above cut. cut = +inf gives kc_objective's results. Same
+ * layouts as kc_objective; KC_EINVAL on bad sizes or a NaN cut. */
+kc_status kc_objective_screen(kc_handle *h, const kc_points *pts, int32_t n_sets, int32_t k,
+                              const float *centers, float cut, double *obj, int64_t *argmax,
+                              void *stream);
 
 /* Algorithm 2 (farthest first traversal) from n_trials starts at once: trial t
  * begins at sample starts[t] and adds, k-1 times, the sample farthest (float64

@@ -18,7 +18,7 @@ NOALLOC_SCRATCH_BYTES = 4 << 20  # KC_NOALLOC_SCRATCH_BYTES
 # every entry point declared in include/kc.h
 EXPORTS = [
     "kc_create", "kc_destroy", "kc_last_error", "kc_rel_margin", "kc_abs_margin",
-    "kc_lower_bound", "kc_lower_bound_noalloc", "kc_objective", "kc_fft", "kc_tighten", "kc_reduce", "kc_autotune", "kc_autotune_tighten",
+    "kc_lower_bound", "kc_lower_bound_noalloc", "kc_objective", "kc_objective_screen", "kc_fft", "kc_tighten", "kc_reduce", "kc_autotune", "kc_autotune_tighten",
     "kc_mlp_forward", "kc_mlp_backward", "kc_mlp_loss", "kc_mlp_adam", "kc_solve",
 ]
 
@@ -92,6 +92,9 @@ def load(path: str = LIB_PATH):
     L.kc_lower_bound_noalloc.argtypes = [vp, P(Points), P(Nodes), vp, vp, vp, vp, vp]
     L.kc_objective.restype = st
     L.kc_objective.argtypes = [vp, P(Points), C.c_int32, C.c_int32, vp, C.c_int32, vp, vp, vp]
+    L.kc_objective_screen.restype = st
+    L.kc_objective_screen.argtypes = [vp, P(Points), C.c_int32, C.c_int32, vp, C.c_float, vp, vp,
+                                      vp]
     L.kc_fft.restype = st
     L.kc_fft.argtypes = [vp, P(Points), C.c_int32, C.c_int32, vp, vp, vp, vp]
     L.kc_tighten.restype = st

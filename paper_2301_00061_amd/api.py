@@ -136,6 +136,23 @@ def objective(x, n, centers: torch.Tensor, precision: int = 32, h: Handle | None
     return obj, am
 
 
+def objective_screen(x, n, centers: torch.Tensor, cut: float, h: Handle | None = None):
+    """Float32 eq (12) screened at `cut` (see kc_objective_screen): exact for
+    sets at or below the cut; a set above it may report a lower value above
+    the cut. Returns (obj f64, argmax i64)."""
+    h = h or handle()
+    P = points(x, n)
+    centers = centers.contiguous()
+    if centers.dim() == 2:
+        centers = centers[None]
+    ns, k = centers.shape[0], centers.shape[1]
+    obj = torch.empty(ns, dtype=torch.float64, device=x.device)
+    am = torch.empty(ns, dtype=torch.int64, device=x.device)
+    h.check(h.lib.kc_objective_screen(h.ptr, C.byref(P), ns, k, _ptr(centers), float(cut),
+                                      _ptr(obj), _ptr(am), _stream()), "kc_objective_screen")
+    return obj, am
+
+
 def tighten(x, n, box_off, lo, hi, alpha, ref_off=None, ref=None, labels=False, k_max=None,
             max_refs=None, h: Handle | None = None):
     """Algorithms 3-4 aggregates per box (see kc_tighten)."""

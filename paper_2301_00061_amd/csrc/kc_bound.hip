@@ -1,5 +1,6 @@
 // kc_bound.hip -- kc_lower_bound / kc_objective entry points, launch sizing
 // and the kernels that reduce the per-split partial results.
+#include <algorithm>
 #include <atomic>
 #include <cmath>
 #include <cstdio>
@@ -138,6 +139,15 @@ using namespace kcb;
 
 static int dmax_of(int d) { return d <= 8 ? d : 16; }
 
+// Tile decisions classify one (node, box) pair per lane: 2^lg_kp(k_max) lanes
+// per node, so a variant with NG nodes per workgroup needs NG << lg <= 64.
+static int lg_kp(int k_max) {
+  int lg = 0;
+  while ((1 << lg) < k_max && lg < 6) ++lg;
+  return lg;
+}
+static bool ts_fits(int NG, int k_max) { return (NG << lg_kp(k_max)) <= 64; }
+
 static int cand_kc(int k_max) {
   if (k_max <= 4) return 4;
   if (k_max <= 8) return 8;
@@ -155,7 +165,7 @@ std::vector<kc_tile> kc_bound_variants(int d, bool with_cand, int k_max) {
     KCB_CAND_VARIANTS(KCB_T3)
 #undef KCB_T3
 #define KCB_T3S(SV, NGV, KCV) \
-  if (KCV == kc && ts) v.push_back({SV, NGV, 8, 1});
+  if (KCV == kc && ts && ts_fits(NGV, k_max)) v.push_back({SV, NGV, 8, 1});
     KCB_CAND_TS_VARIANTS(KCB_T3S)
 #undef KCB_T3S
   } else {
@@ -163,7 +173,7 @@ std::vector<kc_tile> kc_bound_variants(int d, bool with_cand, int k_max) {
     KCB_LB_VARIANTS(KCB_T2)
 #undef KCB_T2
 #define KCB_T2S(SV, NGV) \
-  if (ts) v.push_back({SV, NGV, 8, 1});
+  if (ts && ts_fits(NGV, k_max)) v.push_back({SV, NGV, 8, 1});
     KCB_LB_TS_VARIANTS(KCB_T2S)
 #undef KCB_T2S
   }
@@ -228,16 +238,29 @@ kc_tile kc_default_tile(kc_handle *h, int d, bool with_cand, int n_nodes, int k_
   return {d <= 4 ? 4 : 2, 8, 8};
 }
 
+__global__ void k_zero_u32(uint32_t *p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+// Shared tile-decision values start below every W and above every cw.
+__global__ void k_share_init(uint32_t *gW, int n_nodes, uint32_t *gC, int n_boxes) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_nodes) gW[i] = kcd::FORD_NEG_INF;
+  if (gC && i < n_boxes) gC[i] = kcd::FORD_POS_INF;
+}
+
 kc_status kc_launch_bound(kc_handle *h, const kc_points *p, int mode, int n_nodes, int n_boxes,
                           int k_max, const int32_t *box_off, const float *lo, const float *hi,
                           float *val_raw, double *val_bound, int64_t *argmax, int64_t *cand,
                           const kc_tile &t0, hipStream_t st, void *fixed_scratch,
-                          size_t fixed_bytes) {
+                          size_t fixed_bytes, float cut) {
   const bool point = mode == 1;
   const bool with_cand = cand != nullptr && !point;
   kc_tile t = t0;
   const int DM = dmax_of(p->d);
   const int KC = with_cand ? cand_kc(k_max) : 0;
+  if (t.skip && !ts_fits(t.NG, k_max)) t.skip = 0;
   if (with_cand && !cand_compiled(t.S, t.NG, KC, t.skip, p->d)) t = cand_default(n_nodes, k_max);
   if (!with_cand && !point && !lb_compiled(t.S, t.NG, t.skip, p->d))
     t = kc_default_tile(h, p->d, false, n_nodes, k_max, p->n);
@@ -246,7 +269,7 @@ kc_status kc_launch_bound(kc_handle *h, const kc_points *p, int mode, int n_node
     // for 1..8 attributes
     const bool ok = (t.S == 4 && t.NG == 1) || (t.S == 2 && t.NG == 4) || (t.S == 2 && t.NG == 8);
     if (!ok) t = n_nodes <= 2 ? kc_tile{4, 1, t.bpc, t.skip} : kc_tile{2, 4, t.bpc, t.skip};
-    if (p->d < 1 || p->d > 8) t.skip = 0;
+    if (p->d < 1 || p->d > 8 || !ts_fits(t.NG, k_max)) t.skip = 0;
   }
   size_t lds = (size_t)t.NG * k_max * 2 * DM * sizeof(float);
   while (lds > h->lds_per_block && t.NG > 1) {
@@ -265,17 +288,23 @@ kc_status kc_launch_bound(kc_handle *h, const kc_points *p, int mode, int n_node
   const int64_t grid = splits * n_groups;
   KC_RETURN_IF(grid > 0x7fffffff, h, KC_EUNSUPPORTED, "grid too large");
 
+  const bool screen = point && cut < INFINITY;
   const size_t part_bytes = (size_t)splits * n_nodes * 8;
   const size_t cand_bytes = with_cand ? (size_t)splits * n_boxes * 8 : 0;
+  const size_t dead_bytes = screen ? (((size_t)n_nodes * 4 + 255) & ~(size_t)255) : 0;
+  const size_t gw_bytes = t.skip ? (((size_t)n_nodes * 4 + 255) & ~(size_t)255) : 0;
+  const size_t gc_bytes = t.skip && with_cand ? (((size_t)n_boxes * 4 + 255) & ~(size_t)255) : 0;
+  const size_t share_bytes = dead_bytes + gw_bytes + gc_bytes;
   void *scr = nullptr;
   kc_status s = KC_OK;
   if (fixed_scratch) {
-    KC_RETURN_IF(part_bytes + cand_bytes > fixed_bytes, h, KC_EINVAL,
+    KC_RETURN_IF(screen, h, KC_EINVAL, "screening needs the handle's scratch");
+    KC_RETURN_IF(share_bytes + part_bytes + cand_bytes > fixed_bytes, h, KC_EINVAL,
                  "request needs %zu bytes of scratch, above the %zu-byte static scratch of the "
                  "no-allocation entry point (use fewer nodes or boxes per call)",
-                 part_bytes + cand_bytes, fixed_bytes);
+                 share_bytes + part_bytes + cand_bytes, fixed_bytes);
     scr = fixed_scratch;
-  } else if ((s = kc_get_scratch(h, part_bytes + cand_bytes, &scr)) != KC_OK) {
+  } else if ((s = kc_get_scratch(h, share_bytes + part_bytes + cand_bytes, &scr)) != KC_OK) {
     return s;
   }
 
@@ -292,6 +321,24 @@ kc_status kc_launch_bound(kc_handle *h, const kc_points *p, int mode, int n_node
   A.hi = hi;
   A.n_groups = n_groups;
   A.span = span;
+  A.lg_kp = lg_kp(k_max);
+  A.cut = cut;
+  A.dead = nullptr;
+  A.gW = A.gC = nullptr;
+  if (screen) {
+    A.dead = (uint32_t *)scr;
+    scr = (char *)scr + dead_bytes;
+    k_zero_u32<<<(n_nodes + 255) / 256, 256, 0, st>>>(A.dead, n_nodes);
+    if ((s = kc_check_launch(h, "k_zero_u32")) != KC_OK) return s;
+  }
+  if (t.skip) {
+    A.gW = (uint32_t *)scr;
+    A.gC = gc_bytes ? (uint32_t *)((char *)scr + gw_bytes) : nullptr;
+    scr = (char *)scr + gw_bytes + gc_bytes;
+    const int nmax = std::max(n_nodes, gc_bytes ? n_boxes : 0);
+    k_share_init<<<(nmax + 255) / 256, 256, 0, st>>>(A.gW, n_nodes, A.gC, gc_bytes ? n_boxes : 0);
+    if ((s = kc_check_launch(h, "k_share_init")) != KC_OK) return s;
+  }
   A.part_key = (uint64_t *)scr;
   A.part_cand = with_cand ? (uint64_t *)((char *)scr + part_bytes) : nullptr;
   s = dispatch(p->d, t.S, t.NG, KC, point, t.skip, A, (int)grid, lds, st);
@@ -350,7 +397,8 @@ kc_status kc_autotune_objective(kc_handle *h, const kc_points *p, int n_sets, in
   }
   std::vector<kc_tile> vars;
   for (int skip = 0; skip <= (p->d >= 1 && p->d <= 8 ? 1 : 0); ++skip) {
-#define KCB_T6(SV, NGV) vars.push_back({SV, NGV, 8, skip});
+#define KCB_T6(SV, NGV) \
+  if (!skip || ts_fits(NGV, k)) vars.push_back({SV, NGV, 8, skip});
     KCB_PT_VARIANTS(KCB_T6)
 #undef KCB_T6
   }
@@ -457,6 +505,24 @@ extern "C" kc_status kc_lower_bound_noalloc(kc_handle *h, const kc_points *pts,
     KC_RETURN_IF(!h->noalloc_scratch, h, KC_EDEVICE, "no static scratch on this device");
     return lower_bound_impl(h, pts, nodes, lb_raw, lb_safe, argmax, cand, stream,
                             h->noalloc_scratch, KC_NOALLOC_SCRATCH_BYTES);
+  });
+}
+
+extern "C" kc_status kc_objective_screen(kc_handle *h, const kc_points *pts, int32_t n_sets,
+                                         int32_t k, const float *centers, float cut, double *obj,
+                                         int64_t *argmax, void *stream) {
+  return kc_guard(h, [&]() -> kc_status {
+    if (!h) return KC_EINVAL;
+    kc_status s = kc_validate_points(h, pts);
+    if (s != KC_OK) return s;
+    KC_RETURN_IF(n_sets < 1, h, KC_EINVAL, "n_sets must be >= 1 (got %d)", n_sets);
+    KC_RETURN_IF(k < 1 || k > 64, h, KC_EINVAL, "k must be in [1,64] (got %d)", k);
+    KC_RETURN_IF(!centers, h, KC_EINVAL, "centers is NULL");
+    KC_RETURN_IF(std::isnan(cut), h, KC_EINVAL, "cut is NaN");
+    KC_RETURN_IF(!obj && !argmax, h, KC_EINVAL, "no output requested");
+    const kc_tile t = kc_objective_tile(h, pts, n_sets, k, nullptr);
+    return kc_launch_bound(h, pts, 1, n_sets, n_sets * k, k, nullptr, centers, centers, nullptr,
+                           obj, argmax, nullptr, t, (hipStream_t)stream, nullptr, 0, cut);
   });
 }
 

@@ -36,6 +36,15 @@ struct BoundArgs {
   const float *lo, *hi;    // hi unused in POINT mode
   int n_groups;
   int64_t span;            // samples per split (multiple of WG*S)
+  int lg_kp;               // tile decisions: 2^lg_kp >= k_max lanes per node
+  // POINT screening (dead non-null): a set whose value exceeds `cut` may
+  // stop early; dead[m] != 0 once some wavefront has folded a value above
+  // the cut for set m (read and written by all workgroups).
+  float cut;
+  uint32_t *dead;
+  // TS: per node the largest W and per box the least cw any wavefront has
+  // published (order-preserving encodings; null = no sharing)
+  uint32_t *gW, *gC;
   uint64_t *part_key;      // [splits][n_nodes]
   uint64_t *part_cand;     // [splits][n_boxes] (candidate variants)
 };
@@ -106,16 +115,19 @@ __global__ __launch_bounds__(WG) void k_bound(BoundArgs A) {
     }
   }
 
-  // Tile decisions (TS): per node, W is a value the node's maximum over the
-  // samples already folded has reached (the largest lower bound of a tile's
-  // per-sample values so far), and lane k keeps in cw[jn] a distance to box
-  // k's midpoint that a sample inside the box already folded does not exceed.
-  float W[NG], cw[NG];
-#pragma unroll
-  for (int j = 0; j < NG; ++j) {
-    W[j] = -1.0f;
-    cw[j] = INFINITY;
-  }
+  // Tile decisions (TS), one (node jn, box k) pair per lane (jn = lane >>
+  // lg_kp, k = lane & (2^lg_kp - 1); NG << lg_kp <= 64): Wl is a value node
+  // jn's maximum over the samples already folded has reached (the largest
+  // lower bound of a tile's per-sample values so far), and cwl a distance to
+  // box k's midpoint that a sample inside the box already folded does not
+  // exceed.
+  // Wg and cwg are the values other wavefronts (of any workgroup) have
+  // reached and published in gW / gC, at any index: only a tile strictly
+  // beyond them is settled by them. They are exchanged every 16th tile.
+  const int lg = A.lg_kp;
+  float Wl = -1.0f, cwl = INFINITY, Wg = -1.0f, cwg = INFINITY, Wpub = -1.0f, cpub = INFINITY;
+  uint64_t deadm = 0;  // screening: bit jn, set jn already exceeds the cut
+  int tick = 0;
 
   const int64_t s_lo = (int64_t)split * A.span;
   const int64_t s_hi = min(A.n, s_lo + A.span);
@@ -158,47 +170,69 @@ __global__ __launch_bounds__(WG) void k_bound(BoundArgs A) {
     }
 
     float tlo[DM], thi[DM];
-    bool tile_empty = false;
+    uint64_t skipm = 0;  // bit jn << lg: node jn skips the tile
+    const bool refresh = (tick++ & 15) == 0;
     if constexpr (TS) {
       const int64_t wb = base - lane_off + (int64_t)wave * 64 * S;
-      tile_empty = wb >= s_hi;  // no sample of this wavefront lies in the split
+      if (wb >= s_hi) {
+        skipm = ~0ull;  // no sample of this wavefront lies in the split
+      } else {
 #pragma unroll
-      for (int a = 0; a < DM; ++a) {
-        float l = INFINITY, h = -INFINITY;
-        if (a < dd) {
+        for (int a = 0; a < DM; ++a) {
+          float l = INFINITY, h = -INFINITY;
+          if (a < dd) {
 #pragma unroll
-          for (int i = 0; i < S; ++i)
-            if (base + i < s_hi) {
-              l = fminf(l, xv[a][i]);
-              h = fmaxf(h, xv[a][i]);
-            }
+            for (int i = 0; i < S; ++i)
+              if (base + i < s_hi) {
+                l = fminf(l, xv[a][i]);
+                h = fmaxf(h, xv[a][i]);
+              }
+          }
+          tlo[a] = __int_as_float(__builtin_amdgcn_readfirstlane(
+              __float_as_int(kcd::fdec(kcd::wave_min_u32(kcd::ford(l))))));
+          thi[a] = __int_as_float(__builtin_amdgcn_readfirstlane(
+              __float_as_int(kcd::fdec(kcd::wave_max_u32(kcd::ford(h))))));
         }
-        tlo[a] = __int_as_float(__builtin_amdgcn_readfirstlane(
-            __float_as_int(kcd::fdec(kcd::wave_min_u32(kcd::ford(l))))));
-        thi[a] = __int_as_float(__builtin_amdgcn_readfirstlane(
-            __float_as_int(kcd::fdec(kcd::wave_max_u32(kcd::ford(h))))));
-      }
-    }
-
-#pragma unroll
-    for (int jn = 0; jn < NG; ++jn) {
-      if (m0 + jn >= A.n_nodes) break;
-      const float *bx = smem + jn * per_node;
-      const int cnt = s_cnt[jn];
-      if constexpr (TS) {
-        if (tile_empty) continue;
-        // Lane k bounds, over the tile's range, the distance of box k (the
-        // per-sample operations in the same order on the tile's extreme
-        // coordinates; float32 rounding is monotone): every sample's value
-        // min_k lies in [lb_t, ub_t]. A tile with ub_t < W cannot raise the
-        // maximum (strictly below a value already reached, so not even a tie
-        // at a lower index). With candidates, a box the tile misses, or whose
-        // midpoint lies farther from the whole tile than cw, cannot get its
+        // Lane (jn, k) bounds, over the tile's range, the distance of box k of
+        // node jn (the per-sample operations in the same order on the tile's
+        // extreme coordinates; float32 rounding is monotone): every sample's
+        // min_k of node jn lies in [lb_t, ub_t], the minima of the node's
+        // lanes. W was reached by a sample of an earlier tile of this
+        // wavefront, i.e. at a lower index, so a tile with ub_t <= W cannot
+        // raise the node's maximum nor hold the lowest index attaining it.
+        // With candidates, a box the tile misses, or whose midpoint lies
+        // farther from the whole tile than cw (a distance reached at a lower
+        // index inside the box, so ties too go elsewhere), cannot get its
         // candidate from the tile.
+        const int KP = 1 << lg;
+        const int jn = lane >> lg, k = lane & (KP - 1);
+        const bool valid = jn < NG && m0 + jn < A.n_nodes && k < s_cnt[jn];
+        if (A.gW && refresh && valid) {
+          // Every value ever stored in gW / gC was reached by some wavefront,
+          // and they only move one way, so a stale read is still a valid
+          // (weaker) bound: reads go through the caches; only improvements
+          // are published, with device-scope atomics.
+          if (k == 0) {
+            uint32_t *gw = A.gW + m0 + jn;
+            const uint32_t g = Wl > Wpub ? atomicMax(gw, kcd::ford(Wl))
+                                         : __hip_atomic_load(gw, __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_WORKGROUP);
+            Wpub = fmaxf(Wpub, Wl);
+            Wg = fmaxf(Wg, kcd::fdec(g));
+          }
+          if constexpr (KC > 0) {
+            uint32_t *gc = A.gC + s_beg[jn] + k;
+            const uint32_t g = cwl < cpub ? atomicMin(gc, kcd::ford(cwl))
+                                          : __hip_atomic_load(gc, __ATOMIC_RELAXED,
+                                                              __HIP_MEMORY_SCOPE_WORKGROUP);
+            cpub = fminf(cpub, cwl);
+            cwg = fminf(cwg, kcd::fdec(g));
+          }
+        }
         float lbk = INFINITY, ubk = INFINITY;
         bool cskip = true;
-        if (lane < cnt) {
-          const float *B = bx + lane * 2 * DM;
+        if (valid) {
+          const float *B = smem + jn * per_node + k * 2 * DM;
           float lb = 0.f, ub = 0.f, lm = 0.f, um = 0.f;
           bool ia = true, inn = false;
 #pragma unroll
@@ -223,18 +257,41 @@ __global__ __launch_bounds__(WG) void k_bound(BoundArgs A) {
           lbk = lb;
           ubk = ub;
           if constexpr (KC > 0) {
-            cskip = inn || lm > cw[jn];
-            if (ia) cw[jn] = fminf(cw[jn], um);
+            cskip = inn || lm >= cwl || lm > cwg;
+            if (ia) cwl = fminf(cwl, um);
           }
         }
-        const float lb_t = kcd::fdec(kcd::wave_min_u32(kcd::ford(lbk)));
-        const float ub_t = kcd::fdec(kcd::wave_min_u32(kcd::ford(ubk)));
-        const bool lb_skip = ub_t < W[jn];
-        W[jn] = fmaxf(W[jn], lb_t);
-        bool all_skip = lb_skip;
-        if constexpr (KC > 0) all_skip = all_skip && __ballot(!cskip) == 0;
-        if (all_skip) continue;
+        for (int o = 1; o < KP; o <<= 1) {
+          lbk = fminf(lbk, __shfl_xor(lbk, o));
+          ubk = fminf(ubk, __shfl_xor(ubk, o));
+        }
+        bool ns = ubk <= Wl || ubk < Wg;
+        Wl = fmaxf(Wl, lbk);
+        if constexpr (KC > 0) {
+          const uint64_t seg = KP >= 64 ? ~0ull : ((1ull << KP) - 1ull);
+          ns = ns && ((__ballot(!cskip) >> (jn << lg)) & seg) == 0;
+        }
+        skipm = __ballot(k == 0 && ns);
       }
+    }
+
+    if constexpr (POINT) {
+      // every 16th tile: sets that other workgroups found above the cut
+      if (A.dead && refresh) {
+        uint32_t f = 0;
+        if (lane < NG && m0 + lane < A.n_nodes)
+          f = __hip_atomic_load(A.dead + m0 + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        deadm |= __ballot(f != 0u);
+      }
+    }
+
+#pragma unroll
+    for (int jn = 0; jn < NG; ++jn) {
+      if (m0 + jn >= A.n_nodes) break;
+      const float *bx = smem + jn * per_node;
+      const int cnt = s_cnt[jn];
+      if (TS && ((skipm >> (jn << lg)) & 1ull)) continue;
+      if (POINT && ((deadm >> jn) & 1ull)) continue;
       float best[S];
 #pragma unroll
       for (int i = 0; i < S; ++i) best[i] = INFINITY;
@@ -317,6 +374,15 @@ __global__ __launch_bounds__(WG) void k_bound(BoundArgs A) {
         if (base + i < s_hi && best[i] > rmax[jn]) {
           rmax[jn] = best[i];
           ridx[jn] = (uint32_t)(base + i);
+        }
+      }
+      if constexpr (POINT) {
+        // screening: a value above the cut is folded; the set stops here and,
+        // through dead[], in the other workgroups
+        if (A.dead && __ballot(rmax[jn] > A.cut)) {
+          deadm |= 1ull << jn;
+          if (lane == 0)
+            __hip_atomic_store(A.dead + m0 + jn, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
       }
     }

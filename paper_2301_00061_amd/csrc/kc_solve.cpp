@@ -252,6 +252,19 @@ struct Solver {
   }
 
   double prune_thr() const { return alpha_ub * (1.0 - o.eps_rel); }
+  // Screening threshold of the candidates' float32 objective: a set whose
+  // value v exceeds it has v (1 + rel) + eta > alpha_ub, so it cannot become
+  // the incumbent, and its launch may stop early (reporting the value of some
+  // sample above the threshold, still a lower bound of its objective).
+  float screen_cut() const {
+    if (!(alpha_ub < INFINITY)) return INFINITY;
+    const double rel = kc_rel_margin(D) + 0x1p-50, eta = kc_abs_margin(D);
+    const double c = (alpha_ub - eta) / (1.0 + rel) * (1.0 + 0x1p-40);
+    if (!(c > 0.0)) return 0.0f;
+    float f = (float)c;
+    if ((double)f < c) f = std::nextafter(f, INFINITY);
+    return f;
+  }
 
   // Samples a node is bounded over: its subtree's set, else the active ones.
   kc_points pts_of(const Node *m) const {
@@ -1434,8 +1447,8 @@ struct Solver {
         if (!tuned && (s = kc_autotune_objective(h, &p, (int)gn, K, dxy + i0 * K * D, st)))
           return s;
       }
-      s = kc_objective(h, &p, (int)gn, K, dxy + i0 * K * D, 32, out.dp<double>(o_obj) + i0,
-                       out.dp<int64_t>(o_oam) + i0, st);
+      s = kc_objective_screen(h, &p, (int)gn, K, dxy + i0 * K * D, screen_cut(),
+                              out.dp<double>(o_obj) + i0, out.dp<int64_t>(o_oam) + i0, (void *)st);
       if (s) return s;
       res->passes++;
     }

@@ -713,3 +713,94 @@ def test_bound_every_tile_matches_default(kc, tmp_path, n, d, nn, k, ordered, se
             h.close()
             for a, b in zip(ref, got):
                 assert np.array_equal(a, b), ("objective", S, NG, skip)
+
+
+@pytest.mark.parametrize("seed,n,d,nn,k,nref", [(50, 60001, 2, 12, 3, 4), (51, 40000, 4, 7, 5, 2),
+                                                (52, 30000, 3, 20, 10, 1), (53, 20000, 2, 9, 1, 0),
+                                                (54, 12000, 3, 2, 40, 3), (55, 9000, 12, 3, 3, 1)])
+def test_reduce_tiles_match_per_sample(kc, tmp_path, seed, n, d, nn, k, nref):
+    """The reduction's wavefront tile decisions (on by default) give the
+    per-sample path's flags and compaction bit for bit, on spatially ordered
+    samples where whole tiles are settled, and both lie within the oracle's
+    margin sandwich."""
+    X = datagen.gaussian_mixture(n, d, 3, 0.08, seed)
+    X = np.ascontiguousarray(X[_morton(X)])
+    X64 = X.astype(np.float64)
+    off, lo, hi = datagen.random_boxes(nn, k, d, seed, wmin=0.02, wmax=0.5)
+    nb = lo.shape[0]
+    rng = np.random.default_rng(seed)
+    ref_off = (np.arange(nb + 1) * nref).astype(np.int32)
+    ref = X[rng.integers(0, n, max(1, nb * nref))].astype(np.float32)
+    far = np.stack([np.maximum(np.abs(X64[:, None, :] - lo[off[m]:off[m + 1]][None]),
+                               np.abs(X64[:, None, :] - hi[off[m]:off[m + 1]][None])) ** 2
+                    for m in range(nn)], 0).sum(-1).min(-1).max(0)
+    beta, alpha = float(np.quantile(far, 0.6)), 0.02 * d
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    xd = kc.to_device_soa(X)
+    args = (xd, n, dev(off), dev(lo), dev(hi), beta, alpha, dev(ref_off), dev(ref))
+    kw = dict(want_keep=True, max_refs=max(nref, 1), k_max=k)
+    x1, i1, n1, k1 = kc.reduce(*args, **kw)
+    path = tmp_path / "tune_r.txt"
+    path.write_text(f"r_d{d} 0 0 0 0\n")
+    h = kc.Handle(0, str(path))
+    x0, i0, n0, k0 = kc.reduce(*args, **kw, h=h)
+    h.close()
+    m = int(n1.item())
+    assert int(n0.item()) == m and 0 < m < n
+    assert np.array_equal(k0.cpu().numpy(), k1.cpu().numpy())
+    assert np.array_equal(x0.cpu().numpy()[:, :m], x1.cpu().numpy()[:, :m])
+    assert np.array_equal(i0.cpu().numpy()[:m], i1.cpu().numpy()[:m])
+    g, eta = _g(kc, d)
+    delta = 3 * g + 1e-12
+    oargs = (off, lo.astype(np.float64), hi.astype(np.float64), ref_off, ref.astype(np.float64))
+    keep_o = oracle.reduce_flags(X64, *oargs, beta, alpha)
+    keep_lo = oracle.reduce_flags(X64, *oargs, beta * (1 - delta), alpha * (1 + delta))
+    kg = k1.cpu().numpy()
+    assert np.all(kg >= keep_o) and np.all(kg <= keep_lo)
+
+
+@pytest.mark.parametrize("n,d,ns,k,seed,ordered", [(300_007, 2, 24, 3, 60, True), (200_000, 4, 13, 5, 61, True),
+                                                   (120_001, 3, 9, 8, 62, False), (50_000, 10, 6, 4, 63, True)])
+def test_objective_screen(kc, tmp_path, n, d, ns, k, seed, ordered):
+    """The screened float32 objective: sets at or below the cut get
+    kc_objective's value and argmax bit for bit (every tile, with and without
+    tile decisions); a set above it reports a value above the cut and at most
+    its objective, attained by the reported sample."""
+    X = datagen.gaussian_mixture(n, d, k, 0.08, seed)
+    if ordered:
+        X = np.ascontiguousarray(X[_morton(X)])
+    xd = kc.to_device_soa(X)
+    rng = np.random.default_rng(seed)
+    # half the sets: one sample of each cluster region (low objective); half: random samples
+    means = datagen._means(seed, k, d)
+    near = np.stack([np.argmin(((X - means[j]) ** 2).sum(1)) for j in range(k)])
+    C = X[rng.integers(0, n, (ns, k))].astype(np.float32)
+    C[: ns // 2] = X[near][None] + rng.normal(0, 0.02, (ns // 2, k, d)).astype(np.float32)
+    Cd = torch.from_numpy(np.ascontiguousarray(C)).cuda()
+    obj_e, am_e = (t.cpu().numpy() for t in kc.objective(xd, n, Cd, precision=32))
+    cut = np.float32(np.median(obj_e))
+    below = obj_e <= cut
+    above = obj_e > float(cut) * 1.001
+    assert below.any() and above.any()
+    g, eta = _g(kc, d)
+    X64 = X.astype(np.float64)
+    tiles = [None] + [(S, NG, skip) for S, NG in _PT_TILES for skip in ((0, 1) if 1 <= d <= 8 else (0,))]
+    bn = int(np.log2(ns)) if ns > 1 else 0
+    okey = f"o_d{d}_ns{bn}_k{k}_n{int(np.floor(np.log2(n))) // 2}"
+    for tile in tiles:
+        h = None
+        if tile is not None:
+            path = tmp_path / f"tune_s_{tile[0]}_{tile[1]}_{tile[2]}.txt"
+            path.write_text(f"{okey} {tile[0]} {tile[1]} 8 {tile[2]}\n")
+            h = kc.Handle(0, str(path))
+        o_inf, a_inf = (t.cpu().numpy() for t in kc.objective_screen(xd, n, Cd, float("inf"), h=h))
+        assert np.array_equal(o_inf, obj_e) and np.array_equal(a_inf, am_e), tile
+        o_s, a_s = (t.cpu().numpy() for t in kc.objective_screen(xd, n, Cd, float(cut), h=h))
+        if h is not None:
+            h.close()
+        assert np.array_equal(o_s[below], obj_e[below]) and np.array_equal(a_s[below], am_e[below]), tile
+        for c in np.nonzero(above)[0]:
+            assert float(cut) < o_s[c] <= obj_e[c], (tile, c)
+            v = ((X64[a_s[c]][None] - C[c].astype(np.float64)) ** 2).sum(1).min()
+            # the reported sample attains the reported value (within the margin)
+            assert abs(o_s[c] - v) <= 3 * g * v + 2 * eta, (tile, c)
