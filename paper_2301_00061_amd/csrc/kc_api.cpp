@@ -219,6 +219,13 @@ void kc_tune_load(kc_handle *h) {
   }
 }
 
+void kc_tune_log(const char *key, const kc_tile &t, double ms) {
+  static const bool on = std::getenv("KC_TUNE_VERBOSE") != nullptr;
+  if (on)
+    std::fprintf(stderr, "[kc_tune] %s S=%d NG=%d bpc=%d skip=%d %.4f ms\n", key, t.S, t.NG, t.bpc,
+                 t.skip, ms);
+}
+
 void kc_tune_save(kc_handle *h) {
   if (h->tune_path.empty()) return;
   std::ofstream f(h->tune_path, std::ios::trunc);
@@ -255,6 +262,8 @@ extern "C" kc_status kc_autotune(kc_handle *h, const kc_points *pts, const kc_no
     std::vector<kc_tile> vars = kc_bound_variants(pts->d, wc, nodes->k_max);
     double best = 1e30;
     kc_tile bt = kc_default_tile(h, pts->d, wc, nn, nodes->k_max, pts->n);
+    char key[96];
+    kc_tune_key(key, sizeof(key), pts->d, wc, nn, nodes->k_max, pts->n);
     for (const kc_tile &t : vars) {
       float ms = 0.f;
       double tbest = 1e30;
@@ -272,6 +281,7 @@ extern "C" kc_status kc_autotune(kc_handle *h, const kc_points *pts, const kc_no
         hipEventElapsedTime(&ms, h->ev0, h->ev1);
         if (rep > 0 && ms < tbest) tbest = ms;  // first run is a warm-up
       }
+      if (ok) kc_tune_log(key, t, tbest);
       if (ok && tbest < best) {
         best = tbest;
         bt = t;
@@ -283,8 +293,6 @@ extern "C" kc_status kc_autotune(kc_handle *h, const kc_points *pts, const kc_no
     (void)hipFree(am);
     (void)hipFree(cand);
     h->err[0] = 0;
-    char key[96];
-    kc_tune_key(key, sizeof(key), pts->d, wc, nn, nodes->k_max, pts->n);
     h->tune[key] = bt;
     kc_tune_save(h);
     if (best_ms) *best_ms = best;

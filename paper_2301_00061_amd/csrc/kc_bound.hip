@@ -199,6 +199,21 @@ static bool cand_compiled(int S, int NG, int KC, int skip, int d) {
   return false;
 }
 
+static bool pt_compiled(int S, int NG, int skip) {
+  if (skip) {
+#define KCB_T7S(SV, NGV) \
+  if (S == SV && NG == NGV) return true;
+    KCB_PT_TS_VARIANTS(KCB_T7S)
+#undef KCB_T7S
+    return false;
+  }
+#define KCB_T7(SV, NGV) \
+  if (S == SV && NG == NGV) return true;
+  KCB_PT_VARIANTS(KCB_T7)
+#undef KCB_T7
+  return false;
+}
+
 static bool lb_compiled(int S, int NG, int skip, int d) {
   if (skip) {
     if (d < 1 || d > 8) return false;
@@ -265,11 +280,11 @@ kc_status kc_launch_bound(kc_handle *h, const kc_points *p, int mode, int n_node
   if (!with_cand && !point && !lb_compiled(t.S, t.NG, t.skip, p->d))
     t = kc_default_tile(h, p->d, false, n_nodes, k_max, p->n);
   if (point) {
-    // the float32 objective: (S, NG) of KCB_PT_VARIANTS, with tile decisions
-    // for 1..8 attributes
-    const bool ok = (t.S == 4 && t.NG == 1) || (t.S == 2 && t.NG == 4) || (t.S == 2 && t.NG == 8);
-    if (!ok) t = n_nodes <= 2 ? kc_tile{4, 1, t.bpc, t.skip} : kc_tile{2, 4, t.bpc, t.skip};
+    // the float32 objective: (S, NG) of KCB_PT_VARIANTS, or of
+    // KCB_PT_TS_VARIANTS with tile decisions for 1..8 attributes
     if (p->d < 1 || p->d > 8 || !ts_fits(t.NG, k_max)) t.skip = 0;
+    if (!pt_compiled(t.S, t.NG, t.skip))
+      t = n_nodes <= 2 ? kc_tile{4, 1, t.bpc, 0} : kc_tile{2, 4, t.bpc, 0};
   }
   size_t lds = (size_t)t.NG * k_max * 2 * DM * sizeof(float);
   while (lds > h->lds_per_block && t.NG > 1) {
@@ -396,15 +411,20 @@ kc_status kc_autotune_objective(kc_handle *h, const kc_points *p, int n_sets, in
     return kc_fail(h, KC_ENOMEM, "autotune output buffers");
   }
   std::vector<kc_tile> vars;
-  for (int skip = 0; skip <= (p->d >= 1 && p->d <= 8 ? 1 : 0); ++skip) {
-#define KCB_T6(SV, NGV) \
-  if (!skip || ts_fits(NGV, k)) vars.push_back({SV, NGV, 8, skip});
-    KCB_PT_VARIANTS(KCB_T6)
+#define KCB_T6(SV, NGV) vars.push_back({SV, NGV, 8, 0});
+  KCB_PT_VARIANTS(KCB_T6)
 #undef KCB_T6
+  if (p->d >= 1 && p->d <= 8) {
+#define KCB_T6S(SV, NGV) \
+  if (ts_fits(NGV, k)) vars.push_back({SV, NGV, 8, 1});
+    KCB_PT_TS_VARIANTS(KCB_T6S)
+#undef KCB_T6S
   }
   double best = 1e30;
   kc_tile bt = kc_objective_tile(h, p, n_sets, k, nullptr);
   kc_status s = KC_OK;
+  char key[96];
+  obj_key(key, sizeof(key), p->d, n_sets, k, p->n);
   for (const kc_tile &t : vars) {
     double tbest = 1e30;
     for (int rep = 0; rep < 3 && s == KC_OK; ++rep) {
@@ -419,6 +439,7 @@ kc_status kc_autotune_objective(kc_handle *h, const kc_points *p, int n_sets, in
       if (rep > 0 && ms < tbest) tbest = ms;  // first run is a warm-up
     }
     if (s != KC_OK) break;
+    kc_tune_log(key, t, tbest);
     if (tbest < best) {
       best = tbest;
       bt = t;
@@ -428,8 +449,6 @@ kc_status kc_autotune_objective(kc_handle *h, const kc_points *p, int n_sets, in
   (void)hipFree(obj);
   (void)hipFree(am);
   if (s != KC_OK) return s;
-  char key[96];
-  obj_key(key, sizeof(key), p->d, n_sets, k, p->n);
   h->tune[key] = bt;
   kc_tune_save(h);
   return KC_OK;

@@ -42,17 +42,15 @@ struct BoundArgs {
   // the cut for set m (read and written by all workgroups).
   float cut;
   uint32_t *dead;
-  // TS: per node the largest W and per box the least cw any wavefront has
-  // published (order-preserving encodings; null = no sharing)
+  // tile decisions: per node the largest W and per box the least cw any
+  // wavefront has published (order-preserving encodings; null = no sharing)
   uint32_t *gW, *gC;
   uint64_t *part_key;      // [splits][n_nodes]
   uint64_t *part_cand;     // [splits][n_boxes] (candidate variants)
 };
 
-// TS: wavefront tiles (64 * S consecutive samples) that their bounding box
-// shows cannot raise a node's maximum nor hold a box's best candidate skip the
-// node's per-sample work (see below).
-template <int D, int S, int NG, int KC, bool POINT, bool TS = false>
+// The variants with wavefront tile decisions are k_bound_wide (kc_bound_wide.h).
+template <int D, int S, int NG, int KC, bool POINT>
 __global__ __launch_bounds__(WG) void k_bound(BoundArgs A) {
   constexpr int DM = D ? D : 16;
   constexpr int KCA = KC > 0 ? KC : 1;
@@ -115,26 +113,13 @@ __global__ __launch_bounds__(WG) void k_bound(BoundArgs A) {
     }
   }
 
-  // Tile decisions (TS), one (node jn, box k) pair per lane (jn = lane >>
-  // lg_kp, k = lane & (2^lg_kp - 1); NG << lg_kp <= 64): Wl is a value node
-  // jn's maximum over the samples already folded has reached (the largest
-  // lower bound of a tile's per-sample values so far), and cwl a distance to
-  // box k's midpoint that a sample inside the box already folded does not
-  // exceed.
-  // Wg and cwg are the values other wavefronts (of any workgroup) have
-  // reached and published in gW / gC, at any index: only a tile strictly
-  // beyond them is settled by them. They are exchanged every 16th tile.
-  const int lg = A.lg_kp;
-  float Wl = -1.0f, cwl = INFINITY, Wg = -1.0f, cwg = INFINITY, Wpub = -1.0f, cpub = INFINITY;
   uint64_t deadm = 0;  // screening: bit jn, set jn already exceeds the cut
   int tick = 0;
 
   const int64_t s_lo = (int64_t)split * A.span;
   const int64_t s_hi = min(A.n, s_lo + A.span);
   const int64_t lane_off = (int64_t)tid * S;
-  // with tile decisions every lane runs the same number of tiles
-  for (int64_t base = s_lo + lane_off; (TS ? base - lane_off : base) < s_hi;
-       base += (int64_t)WG * S) {
+  for (int64_t base = s_lo + lane_off; base < s_hi; base += (int64_t)WG * S) {
     float xv[DM][S];
     const bool full = base + S <= s_hi;
 #pragma unroll
@@ -169,112 +154,7 @@ __global__ __launch_bounds__(WG) void k_bound(BoundArgs A) {
       }
     }
 
-    float tlo[DM], thi[DM];
-    uint64_t skipm = 0;  // bit jn << lg: node jn skips the tile
     const bool refresh = (tick++ & 15) == 0;
-    if constexpr (TS) {
-      const int64_t wb = base - lane_off + (int64_t)wave * 64 * S;
-      if (wb >= s_hi) {
-        skipm = ~0ull;  // no sample of this wavefront lies in the split
-      } else {
-#pragma unroll
-        for (int a = 0; a < DM; ++a) {
-          float l = INFINITY, h = -INFINITY;
-          if (a < dd) {
-#pragma unroll
-            for (int i = 0; i < S; ++i)
-              if (base + i < s_hi) {
-                l = fminf(l, xv[a][i]);
-                h = fmaxf(h, xv[a][i]);
-              }
-          }
-          tlo[a] = __int_as_float(__builtin_amdgcn_readfirstlane(
-              __float_as_int(kcd::fdec(kcd::wave_min_u32(kcd::ford(l))))));
-          thi[a] = __int_as_float(__builtin_amdgcn_readfirstlane(
-              __float_as_int(kcd::fdec(kcd::wave_max_u32(kcd::ford(h))))));
-        }
-        // Lane (jn, k) bounds, over the tile's range, the distance of box k of
-        // node jn (the per-sample operations in the same order on the tile's
-        // extreme coordinates; float32 rounding is monotone): every sample's
-        // min_k of node jn lies in [lb_t, ub_t], the minima of the node's
-        // lanes. W was reached by a sample of an earlier tile of this
-        // wavefront, i.e. at a lower index, so a tile with ub_t <= W cannot
-        // raise the node's maximum nor hold the lowest index attaining it.
-        // With candidates, a box the tile misses, or whose midpoint lies
-        // farther from the whole tile than cw (a distance reached at a lower
-        // index inside the box, so ties too go elsewhere), cannot get its
-        // candidate from the tile.
-        const int KP = 1 << lg;
-        const int jn = lane >> lg, k = lane & (KP - 1);
-        const bool valid = jn < NG && m0 + jn < A.n_nodes && k < s_cnt[jn];
-        if (A.gW && refresh && valid) {
-          // Every value ever stored in gW / gC was reached by some wavefront,
-          // and they only move one way, so a stale read is still a valid
-          // (weaker) bound: reads go through the caches; only improvements
-          // are published, with device-scope atomics.
-          if (k == 0) {
-            uint32_t *gw = A.gW + m0 + jn;
-            const uint32_t g = Wl > Wpub ? atomicMax(gw, kcd::ford(Wl))
-                                         : __hip_atomic_load(gw, __ATOMIC_RELAXED,
-                                                             __HIP_MEMORY_SCOPE_WORKGROUP);
-            Wpub = fmaxf(Wpub, Wl);
-            Wg = fmaxf(Wg, kcd::fdec(g));
-          }
-          if constexpr (KC > 0) {
-            uint32_t *gc = A.gC + s_beg[jn] + k;
-            const uint32_t g = cwl < cpub ? atomicMin(gc, kcd::ford(cwl))
-                                          : __hip_atomic_load(gc, __ATOMIC_RELAXED,
-                                                              __HIP_MEMORY_SCOPE_WORKGROUP);
-            cpub = fminf(cpub, cwl);
-            cwg = fminf(cwg, kcd::fdec(g));
-          }
-        }
-        float lbk = INFINITY, ubk = INFINITY;
-        bool cskip = true;
-        if (valid) {
-          const float *B = smem + jn * per_node + k * 2 * DM;
-          float lb = 0.f, ub = 0.f, lm = 0.f, um = 0.f;
-          bool ia = true, inn = false;
-#pragma unroll
-          for (int a = 0; a < DM; ++a) {
-            if (a < dd) {
-              const float l = B[2 * a], h = POINT ? l : B[2 * a + 1];
-              const float gl = fmaxf(fmaxf(l - thi[a], tlo[a] - h), 0.f);
-              const float ul = fmaxf(fmaxf(l - tlo[a], thi[a] - h), 0.f);
-              lb = (a == 0) ? gl * gl : __builtin_fmaf(gl, gl, lb);
-              ub = (a == 0) ? ul * ul : __builtin_fmaf(ul, ul, ub);
-              if constexpr (KC > 0) {
-                const float mid = 0.5f * (l + h);
-                const float gm = fmaxf(fmaxf(mid - thi[a], tlo[a] - mid), 0.f);
-                const float um2 = fmaxf(thi[a] - mid, mid - tlo[a]);
-                lm = (a == 0) ? gm * gm : __builtin_fmaf(gm, gm, lm);
-                um = (a == 0) ? um2 * um2 : __builtin_fmaf(um2, um2, um);
-                ia = ia && l <= tlo[a] && thi[a] <= h;
-                inn = inn || thi[a] < l || tlo[a] > h;
-              }
-            }
-          }
-          lbk = lb;
-          ubk = ub;
-          if constexpr (KC > 0) {
-            cskip = inn || lm >= cwl || lm > cwg;
-            if (ia) cwl = fminf(cwl, um);
-          }
-        }
-        for (int o = 1; o < KP; o <<= 1) {
-          lbk = fminf(lbk, __shfl_xor(lbk, o));
-          ubk = fminf(ubk, __shfl_xor(ubk, o));
-        }
-        bool ns = ubk <= Wl || ubk < Wg;
-        Wl = fmaxf(Wl, lbk);
-        if constexpr (KC > 0) {
-          const uint64_t seg = KP >= 64 ? ~0ull : ((1ull << KP) - 1ull);
-          ns = ns && ((__ballot(!cskip) >> (jn << lg)) & seg) == 0;
-        }
-        skipm = __ballot(k == 0 && ns);
-      }
-    }
-
     if constexpr (POINT) {
       // every 16th tile: sets that other workgroups found above the cut
       if (A.dead && refresh) {
@@ -290,7 +170,6 @@ __global__ __launch_bounds__(WG) void k_bound(BoundArgs A) {
       if (m0 + jn >= A.n_nodes) break;
       const float *bx = smem + jn * per_node;
       const int cnt = s_cnt[jn];
-      if (TS && ((skipm >> (jn << lg)) & 1ull)) continue;
       if (POINT && ((deadm >> jn) & 1ull)) continue;
       float best[S];
 #pragma unroll
@@ -503,6 +382,8 @@ __global__ __launch_bounds__(WG) void k_obj64(Obj64Args A) {
 
 }  // namespace kcb
 
+#include "kc_bound_wide.h"
+
 // Launch variants: (S, NG) for the lower bound and the float32 objective,
 // (S, NG, KC) for the lower bound with candidates (KC >= boxes per node).
 #define KCB_LB_VARIANTS(X) X(8, 1) X(4, 1) X(2, 1) X(4, 2) X(4, 4) X(2, 4) X(4, 8) X(2, 8) X(2, 16) X(1, 16)
@@ -518,16 +399,18 @@ __global__ __launch_bounds__(WG) void k_obj64(Obj64Args A) {
 #define KCB_CAND_CASE(SV, NGV, KCV) \
   if (S == SV && NG == NGV && KC == KCV) { k_bound<DV_, SV, NGV, KCV, false><<<g, b, lds, st>>>(A); return KC_OK; }
 
-// Variants with tile decisions (attribute counts 1..8).
-#define KCB_LB_TS_VARIANTS(X) X(8, 1) X(4, 1) X(4, 4) X(4, 8) X(2, 8)
-#define KCB_PT_TS_VARIANTS(X) X(4, 1) X(2, 4) X(2, 8)
-#define KCB_CAND_TS_VARIANTS(X) X(2, 8, 4) X(2, 4, 4) X(4, 4, 4) X(4, 2, 8) X(2, 2, 8) X(2, 4, 8)
+// Variants with tile decisions (k_bound_wide; attribute counts 1..8; usable
+// when NG << lg_kp <= 64).
+#define KCB_LB_TS_VARIANTS(X) X(8, 16) X(4, 16) X(8, 8) X(4, 8) X(4, 4) X(8, 1)
+#define KCB_PT_TS_VARIANTS(X) X(4, 16) X(8, 8) X(4, 8) X(4, 4) X(8, 1)
+#define KCB_CAND_TS_VARIANTS(X) \
+  X(4, 16, 4) X(2, 16, 4) X(4, 8, 4) X(4, 8, 8) X(2, 8, 8) X(4, 4, 8) X(4, 4, 16) X(2, 4, 16) X(4, 1, 64)
 #define KCB_LB_TS_CASE(SV, NGV) \
-  if (S == SV && NG == NGV) { k_bound<DV, SV, NGV, 0, false, true><<<g, b, lds, st>>>(A); return KC_OK; }
+  if (S == SV && NG == NGV) { k_bound_wide<DV, SV, NGV, 0, false><<<g, b, lds, st>>>(A); return KC_OK; }
 #define KCB_PT_TS_CASE(SV, NGV) \
-  if (S == SV && NG == NGV) { k_bound<DV, SV, NGV, 0, true, true><<<g, b, lds, st>>>(A); return KC_OK; }
+  if (S == SV && NG == NGV) { k_bound_wide<DV, SV, NGV, 0, true><<<g, b, lds, st>>>(A); return KC_OK; }
 #define KCB_CAND_TS_CASE(SV, NGV, KCV) \
-  if (S == SV && NG == NGV && KC == KCV) { k_bound<DV, SV, NGV, KCV, false, true><<<g, b, lds, st>>>(A); return KC_OK; }
+  if (S == SV && NG == NGV && KC == KCV) { k_bound_wide<DV, SV, NGV, KCV, false><<<g, b, lds, st>>>(A); return KC_OK; }
 
 namespace kcb {
 template <int DV>

@@ -98,6 +98,8 @@ kc_tile kc_default_tile(kc_handle *h, int d, bool with_cand, int n_nodes, int k_
 void kc_tune_key(char *buf, size_t size, int d, bool with_cand, int n_nodes, int k_max, int64_t n);
 void kc_tune_load(kc_handle *h);
 void kc_tune_save(kc_handle *h);
+// Prints one autotune measurement to stderr when KC_TUNE_VERBOSE is set.
+void kc_tune_log(const char *key, const kc_tile &t, double ms);
 
 // Tile of a tightening launch (kc_tighten.hip): the autotuner's choice for the
 // shape bucket (*tuned = true), else the default; kc_tile.bpc holds the

@@ -66,6 +66,196 @@ __global__ void k_tighten_decode(uint32_t *a, uint32_t *b, uint32_t *c, uint32_t
   }
 }
 
+// ---------------------------------------------------------------------------
+// Inside-only tightening. In a batch without refs, a node of two or more
+// boxes whose center-based bound stays within alpha for every box over a set
+// of samples excludes none of them from any box, so none is assigned or
+// excluded (their label is -1, Algorithm 3) and they belong to S_+^k exactly
+// when they lie inside box k (Algorithm 4 without refs). For such (node,
+// chunk of LCHUNK samples) pairs only the inside test and the bounding-box
+// fold are needed: k_tighten_inside does them, with a fraction of the full
+// kernel's registers and instructions, and marks the pair in a map that the
+// full kernel reads to skip it. k_chunk_bbox gives each chunk's bounding
+// box; the decision applies the per-sample operations in the same order to
+// the bounding box's extreme coordinates (float32 rounding is monotone, so
+// no sample's bound exceeds the chunk's).
+
+__global__ __launch_bounds__(256) void k_chunk_bbox(const float *x, int64_t n, int64_t ld, int d,
+                                                    float *cbb) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ uint32_t s_lo[4][16], s_hi[4][16];
+  const int64_t c0 = (int64_t)blockIdx.x * LCHUNK;
+  for (int a = 0; a < d; ++a) {
+    const float *p = x + (int64_t)a * ld;
+    float l = INFINITY, h = -INFINITY;
+#pragma unroll
+    for (int j = 0; j < LCHUNK / 256; ++j) {
+      const int64_t i = c0 + j * 256 + tid;
+      if (i < n) {
+        l = fminf(l, p[i]);
+        h = fmaxf(h, p[i]);
+      }
+    }
+    const uint32_t wl = kcd::wave_min_u32(kcd::ford(l)), wh = kcd::wave_max_u32(kcd::ford(h));
+    if (lane == 0) {
+      s_lo[wave][a] = wl;
+      s_hi[wave][a] = wh;
+    }
+  }
+  __syncthreads();
+  if (tid < d) {
+    uint32_t l = s_lo[0][tid], h = s_hi[0][tid];
+    for (int w = 1; w < 4; ++w) {
+      l = min(l, s_lo[w][tid]);
+      h = max(h, s_hi[w][tid]);
+    }
+    cbb[((int64_t)blockIdx.x * 2) * d + tid] = kcd::fdec(l);
+    cbb[((int64_t)blockIdx.x * 2 + 1) * d + tid] = kcd::fdec(h);
+  }
+}
+
+// One node and one split of whole chunks per workgroup: per chunk, the
+// decision from its bounding box, then (when it holds) per lane the count and
+// bounding box of its samples inside each box.
+template <int D, int KC, int S>
+__global__ __launch_bounds__(WG) void k_tighten_inside(TightenArgs A, const float *cbb,
+                                                       uint8_t *map, int64_t chunks_per_split) {
+  __shared__ float sb[KC][2][D];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int u = kcd::xcd_unit(blockIdx.x, gridDim.x);
+  const int m = u % A.n_nodes, split = u / A.n_nodes;
+  const int b0 = kcd::clampi(A.box_off[m], 0, A.n_boxes);
+  const int b1 = kcd::clampi(A.box_off[m + 1], b0, A.n_boxes);
+  const int cnt = min(min(b1 - b0, A.k_max), KC);
+  for (int i = tid; i < KC * D; i += WG) {
+    const int k = i / D, a = i - k * D;
+    sb[k][0][a] = k < cnt ? A.lo[(int64_t)(b0 + k) * D + a] : 0.f;
+    sb[k][1][a] = k < cnt ? A.hi[(int64_t)(b0 + k) * D + a] : 0.f;
+  }
+  __syncthreads();
+  float bmin[KC][D], bmax[KC][D];
+  uint32_t nin[KC];
+#pragma unroll
+  for (int k = 0; k < KC; ++k) {
+    nin[k] = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      bmin[k][a] = INFINITY;
+      bmax[k][a] = -INFINITY;
+    }
+  }
+  const int64_t cb0 = (int64_t)split * chunks_per_split;
+  const int64_t cb1 = min(A.n_lchunks, cb0 + chunks_per_split);
+  for (int64_t c = cb0; c < cb1; ++c) {
+    // the chunk's decision (uniform): every box's center-based bound over the
+    // chunk's bounding box within alpha
+    bool light = cnt >= 2;
+    for (int k = 0; k < cnt && light; ++k) {
+      float ub = 0.f;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        const float blo = cbb[(c * 2) * D + a], bhi = cbb[(c * 2 + 1) * D + a];
+        const float uu = fmaxf(fmaxf(sb[k][0][a] - blo, bhi - sb[k][1][a]), 0.f);
+        ub = (a == 0) ? uu * uu : __builtin_fmaf(uu, uu, ub);
+      }
+      light = !(ub > A.t_center);
+    }
+    if (tid == 0) map[(int64_t)m * A.n_lchunks + c] = light ? 1 : 0;
+    if (!light) continue;
+    const int64_t s_hi = min(A.n, (c + 1) * (int64_t)LCHUNK);
+    for (int64_t base = c * (int64_t)LCHUNK + (int64_t)tid * S; base < s_hi;
+         base += (int64_t)WG * S) {
+      float xs[S][D];
+      const bool full = base + S <= s_hi;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        const float *p = A.x + (int64_t)a * A.ld + base;
+        if (full && S == 4) {
+          const float4 v = *reinterpret_cast<const float4 *>(p);
+          xs[0][a] = v.x;
+          xs[1 % S][a] = v.y;
+          xs[2 % S][a] = v.z;
+          xs[3 % S][a] = v.w;
+        } else if (full && S == 2) {
+          const float2 v = *reinterpret_cast<const float2 *>(p);
+          xs[0][a] = v.x;
+          xs[1 % S][a] = v.y;
+        } else {
+#pragma unroll
+          for (int i = 0; i < S; ++i) xs[i][a] = (base + i < s_hi) ? p[i] : 0.f;
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < KC; ++k) {
+        if (k >= cnt) break;
+        float l[D], h[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          l[a] = sb[k][0][a];
+          h[a] = sb[k][1][a];
+        }
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+          bool in = base + i < s_hi;
+#pragma unroll
+          for (int a = 0; a < D; ++a) in = in && l[a] <= xs[i][a] && xs[i][a] <= h[a];
+          if (in) {
+            ++nin[k];
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+              bmin[k][a] = fminf(bmin[k][a], xs[i][a]);
+              bmax[k][a] = fmaxf(bmax[k][a], xs[i][a]);
+            }
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < KC; ++k) {
+    const uint32_t ci = kcd::wave_sum_u32(nin[k]);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const uint32_t v0 = kcd::wave_min_u32(kcd::ford(bmin[k][a]));
+      const uint32_t v1 = kcd::wave_max_u32(kcd::ford(bmax[k][a]));
+      if (lane == 0 && k < cnt && ci) {
+        const int64_t o = (int64_t)(b0 + k) * D + a;
+        atomicMin(&A.bb_lo[o], v0);
+        atomicMax(&A.bb_hi[o], v1);
+      }
+    }
+    if (lane == 0 && k < cnt && ci) atomicAdd(&A.n_in[b0 + k], ci);
+  }
+}
+
+template <int D>
+static bool launch_inside_d(int kc, const TightenArgs &A, const float *cbb, uint8_t *map,
+                            int64_t cps, int grid, hipStream_t st) {
+  constexpr int S = D <= 4 ? 4 : 2;
+#define KCT_IN(KV) \
+  case KV: k_tighten_inside<D, KV, S><<<grid, WG, 0, st>>>(A, cbb, map, cps); return true;
+  switch (kc) {
+    KCT_IN(1) KCT_IN(2) KCT_IN(3) KCT_IN(4) KCT_IN(5) KCT_IN(6) KCT_IN(8)
+    default: return false;
+  }
+#undef KCT_IN
+}
+
+static bool launch_inside(int d, int kc, const TightenArgs &A, const float *cbb, uint8_t *map,
+                          int64_t cps, int grid, hipStream_t st) {
+  switch (d) {
+    case 1: return launch_inside_d<1>(kc, A, cbb, map, cps, grid, st);
+    case 2: return launch_inside_d<2>(kc, A, cbb, map, cps, grid, st);
+    case 3: return launch_inside_d<3>(kc, A, cbb, map, cps, grid, st);
+    case 4: return launch_inside_d<4>(kc, A, cbb, map, cps, grid, st);
+    case 5: return launch_inside_d<5>(kc, A, cbb, map, cps, grid, st);
+    case 6: return launch_inside_d<6>(kc, A, cbb, map, cps, grid, st);
+    case 7: return launch_inside_d<7>(kc, A, cbb, map, cps, grid, st);
+    case 8: return launch_inside_d<8>(kc, A, cbb, map, cps, grid, st);
+    default: return false;
+  }
+}
+
 static const int kKC[] = {1, 2, 3, 4, 5, 6, 8};
 
 // Boxes per chunk: all boxes of a node when their aggregates fit in about 160
@@ -125,6 +315,9 @@ struct Launch {
   size_t lds;
   bool refs;
   int64_t nbd, nmax;
+  bool inside;  // try the inside-only kernel on the (node, chunk) pairs it settles
+  int grid_inside;
+  int64_t cps, n_lchunks;  // chunks per split of the inside-only kernel; chunks
 };
 
 // Validates the request and sizes a launch with tile t (NG > 1 only when all
@@ -189,6 +382,19 @@ static kc_status plan(kc_handle *h, const kc_points *pts, const kc_nodes *nodes,
   const int64_t ni = L.nbd > nodes->n_boxes ? L.nbd : nodes->n_boxes;
   L.nmax = ni > nodes->n_nodes ? ni : nodes->n_nodes;
   L.t = t;
+  // batched launches without refs whose boxes fit one chunk, 1..8 attributes
+  L.inside = !refs && n_chunks == 1 && !labels && d >= 1 && d <= 8 && nodes->n_nodes >= 8;
+  L.grid_inside = 0;
+  L.cps = 0;
+  if (L.inside) {
+    const int64_t nch = (pts->n + LCHUNK - 1) / LCHUNK;
+    int64_t sp = (target + nodes->n_nodes - 1) / nodes->n_nodes;
+    L.cps = (nch + sp - 1) / sp;
+    sp = (nch + L.cps - 1) / L.cps;
+    L.inside = sp * nodes->n_nodes <= 0x7fffffff;
+    L.grid_inside = (int)(sp * nodes->n_nodes);
+    L.n_lchunks = nch;
+  }
   return KC_OK;
 }
 
@@ -213,6 +419,24 @@ static kc_status run(kc_handle *h, Launch &L, float *bb_lo, float *bb_hi,
   A.n_excl = n_excl;
   A.asg_far = (uint64_t *)asg_far;
   A.labels = labels;
+  A.light_map = nullptr;
+  A.n_lchunks = 0;
+  if (L.inside) {
+    const int d = A.d;
+    const size_t cbb_bytes = ((size_t)L.n_lchunks * 2 * d * 4 + 255) & ~(size_t)255;
+    const size_t map_bytes = (size_t)A.n_nodes * L.n_lchunks;
+    void *scr = nullptr;
+    if ((s = kc_get_scratch(h, cbb_bytes + map_bytes, &scr)) != KC_OK) return s;
+    float *cbb = (float *)scr;
+    uint8_t *map = (uint8_t *)scr + cbb_bytes;
+    k_chunk_bbox<<<(unsigned)L.n_lchunks, 256, 0, st>>>(A.x, A.n, A.ld, d, cbb);
+    if ((s = kc_check_launch(h, "k_chunk_bbox")) != KC_OK) return s;
+    A.n_lchunks = L.n_lchunks;
+    KC_RETURN_IF(!launch_inside(d, L.kc, A, cbb, map, L.cps, L.grid_inside, st), h,
+                 KC_EUNSUPPORTED, "no inside-only tighten variant for d=%d kc=%d", d, L.kc);
+    if ((s = kc_check_launch(h, "k_tighten_inside")) != KC_OK) return s;
+    A.light_map = map;
+  }
   const kc_tile &t = L.t;
   KC_RETURN_IF(!dispatch(A.d, L.kc, t.S, t.NG, t.bpc, t.skip, L.refs, A, L.grid, L.lds, st), h,
                KC_EUNSUPPORTED, "no tighten variant for d=%d kc=%d S=%d NG=%d", A.d, L.kc, t.S, t.NG);
@@ -298,6 +522,8 @@ extern "C" kc_status kc_autotune_tighten(kc_handle *h, const kc_points *pts, con
     const bool single = (nodes->k_max + kc - 1) / kc == 1;
     double best = 1e30;
     kc_tile bt = tighten_variants(d, kc, single)[0];
+    char key[96];
+    tighten_key(key, sizeof(key), d, nodes->k_max, nn, pts->n, refs != nullptr);
     for (const kc_tile &t : tighten_variants(d, kc, single)) {
       Launch L;
       s = plan(h, pts, nodes, alpha, refs, false, t, L);
@@ -316,6 +542,7 @@ extern "C" kc_status kc_autotune_tighten(kc_handle *h, const kc_points *pts, con
         if (rep > 0 && ms < tbest) tbest = ms;  // first run is a warm-up
       }
       if (s != KC_OK) break;
+      kc_tune_log(key, t, tbest);
       if (tbest < best) {
         best = tbest;
         bt = t;
@@ -324,8 +551,6 @@ extern "C" kc_status kc_autotune_tighten(kc_handle *h, const kc_points *pts, con
     (void)hipStreamSynchronize(st);
     (void)hipFree(buf);
     if (s != KC_OK) return s;
-    char key[96];
-    tighten_key(key, sizeof(key), d, nodes->k_max, nn, pts->n, refs != nullptr);
     h->tune[key] = bt;
     kc_tune_save(h);
     if (best_ms) *best_ms = best;

@@ -41,13 +41,20 @@ struct TightenArgs {
   float t_ball;    // dist <= t_ball     => inside the ball of the ref (alpha)
   int n_chunks, kc;  // boxes per chunk (n_chunks > 1 only with NG = 1)
   int n_groups;      // node groups of NG nodes
+  // (node, chunk of LCHUNK samples) pairs the inside-only kernel handled
+  // (nullable, [n_nodes][n_lchunks]): there the center-based test provably
+  // excludes nothing, so this kernel skips them
   int node_floats;   // LDS floats per node slot
   int64_t span;
   uint32_t *bb_lo, *bb_hi, *asg_min, *asg_max;  // order-preserving encodings
   uint32_t *n_in, *n_asg, *n_excl;
   uint64_t *asg_far;  // per box: max key (dist to midpoint, ~index); may be null
   int8_t *labels;
+  const uint8_t *light_map;
+  int64_t n_lchunks;
 };
+
+constexpr int LCHUNK = 4096;  // samples per chunk of the inside-only decisions
 
 __device__ __forceinline__ float sqdist(const float *xv, const float *r, int dd, int DM) {
   float acc = 0.f;
@@ -458,6 +465,7 @@ __global__ __launch_bounds__(WG, MINW > 0 ? MINW : 1) void k_tighten(TightenArgs
     allref[jn] = __builtin_amdgcn_readfirstlane(s_node[jn].allref) != 0;
   }
   const bool write_labels = A.labels != nullptr && chunk == 0 && NG == 1;
+  static_assert(LCHUNK % (64 * S) == 0, "a wavefront's tile lies in one chunk");
 
   const int64_t s_lo = (int64_t)split * A.span;
   const int64_t s_hi = min(A.n, s_lo + A.span);
@@ -527,6 +535,9 @@ __global__ __launch_bounds__(WG, MINW > 0 ? MINW : 1) void k_tighten(TightenArgs
 #pragma unroll
     for (int jn = 0; jn < NG; ++jn) {
       if (m0 + jn >= A.n_nodes) break;  // workgroup-uniform
+      if (A.light_map && tb + (int64_t)wave * 64 * S < s_hi &&
+          A.light_map[(int64_t)(m0 + jn) * A.n_lchunks + (tb + (int64_t)wave * 64 * S) / LCHUNK])
+        continue;  // the inside-only kernel took this node's chunk
       bool done = false;
       if constexpr (TSKIP) {
         if (nval == 0) {

@@ -225,6 +225,11 @@ def _tighten_case(seed, n, d, k, nn=1, with_refs=True, alpha_scale=1.2, ordered=
     (10, 40000, 2, 3, 1, True, True, 1.2), (11, 30001, 3, 5, 4, True, True, 0.6),
     (12, 20000, 4, 5, 6, False, True, 1.2), (13, 7777, 2, 3, 2, True, True, 0.3),
     (14, 50000, 5, 4, 3, True, True, 2.0),
+    # batches of 8+ nodes without refs and a large alpha: nodes whose boxes
+    # the center-based test cannot exclude any sample from take the
+    # inside-only kernel, the others the full one
+    (15, 30000, 2, 3, 12, False, True, 8.0), (16, 25000, 4, 5, 10, False, True, 3.0),
+    (17, 20000, 3, 2, 9, False, False, 2.0), (18, 12000, 5, 8, 8, False, True, 6.0),
     # several refs per box (up to the 50 of Section 4.1.2): the refs' bounding
     # box, the extremes-first order and the per-ref scans
     (20, 20000, 2, 3, 1, 7, False, 0.4), (21, 30000, 3, 4, 3, 50, False, 0.5),
@@ -653,11 +658,13 @@ def test_tighten_every_tile_matches_default(kc, tmp_path, seed, n, d, k, nn, wit
 
 
 _LB_TILES = [(8, 1), (4, 1), (2, 1), (4, 2), (4, 4), (2, 4), (4, 8), (2, 8), (2, 16), (1, 16)]
-_LB_TS_TILES = [(8, 1), (4, 1), (4, 4), (4, 8), (2, 8)]
+_LB_TS_TILES = [(8, 16), (4, 16), (8, 8), (4, 8), (4, 4), (8, 1)]
 _CAND_TILES = [(2, 8, 4), (2, 4, 4), (2, 1, 4), (4, 4, 4), (4, 2, 4), (2, 4, 8), (2, 2, 8), (2, 1, 8),
                (4, 2, 8), (1, 4, 8), (1, 2, 16), (1, 1, 16), (1, 1, 64)]
-_CAND_TS_TILES = [(2, 8, 4), (2, 4, 4), (4, 4, 4), (4, 2, 8), (2, 2, 8), (2, 4, 8)]
+_CAND_TS_TILES = [(4, 16, 4), (2, 16, 4), (4, 8, 4), (4, 8, 8), (2, 8, 8), (4, 4, 8), (4, 4, 16),
+                  (2, 4, 16), (4, 1, 64)]
 _PT_TILES = [(4, 1), (2, 4), (2, 8)]
+_PT_TS_TILES = [(4, 16), (8, 8), (4, 8), (4, 4), (8, 1)]
 
 
 def _bound_key(d, cand, nn, k, n):
@@ -704,15 +711,14 @@ def test_bound_every_tile_matches_default(kc, tmp_path, n, d, nn, k, ordered, se
     ref = [t.cpu().numpy() for t in kc.objective(xd, n, dev(C), precision=32)]
     bn = int(np.log2(nn)) if nn > 1 else 0
     okey = f"o_d{d}_ns{bn}_k{k}_n{int(np.floor(np.log2(n))) // 2}"
-    for S, NG in _PT_TILES:
-        for skip in (0, 1) if ts else (0,):
-            path = tmp_path / f"tune_o_{S}_{NG}_{skip}.txt"
-            path.write_text(f"{okey} {S} {NG} 8 {skip}\n")
-            h = kc.Handle(0, str(path))
-            got = [t.cpu().numpy() for t in kc.objective(xd, n, dev(C), precision=32, h=h)]
-            h.close()
-            for a, b in zip(ref, got):
-                assert np.array_equal(a, b), ("objective", S, NG, skip)
+    for S, NG, skip in [(S, NG, 0) for S, NG in _PT_TILES] + [(S, NG, 1) for S, NG in _PT_TS_TILES if ts]:
+        path = tmp_path / f"tune_o_{S}_{NG}_{skip}.txt"
+        path.write_text(f"{okey} {S} {NG} 8 {skip}\n")
+        h = kc.Handle(0, str(path))
+        got = [t.cpu().numpy() for t in kc.objective(xd, n, dev(C), precision=32, h=h)]
+        h.close()
+        for a, b in zip(ref, got):
+            assert np.array_equal(a, b), ("objective", S, NG, skip)
 
 
 @pytest.mark.parametrize("seed,n,d,nn,k,nref", [(50, 60001, 2, 12, 3, 4), (51, 40000, 4, 7, 5, 2),
@@ -784,7 +790,8 @@ def test_objective_screen(kc, tmp_path, n, d, ns, k, seed, ordered):
     assert below.any() and above.any()
     g, eta = _g(kc, d)
     X64 = X.astype(np.float64)
-    tiles = [None] + [(S, NG, skip) for S, NG in _PT_TILES for skip in ((0, 1) if 1 <= d <= 8 else (0,))]
+    tiles = [None] + [(S, NG, 0) for S, NG in _PT_TILES]
+    tiles += [(S, NG, 1) for S, NG in _PT_TS_TILES if 1 <= d <= 8]
     bn = int(np.log2(ns)) if ns > 1 else 0
     okey = f"o_d{d}_ns{bn}_k{k}_n{int(np.floor(np.log2(n))) // 2}"
     for tile in tiles:
