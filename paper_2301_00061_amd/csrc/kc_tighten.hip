@@ -274,9 +274,16 @@ static int choose_kc(int d, int k_max) {
 
 static int dsupp(int d) { return d <= 8 ? d : 0; }
 
-// The compiled tiles (S, NG, occupancy) for this attribute count and chunk
-// (the same table as launch_kc in kc_tighten_impl.h).
-static std::vector<kc_tile> tighten_variants(int d, int kc, bool single) {
+static int lg_kp(int k_max) {
+  int lg = 0;
+  while ((1 << lg) < k_max && lg < 6) ++lg;
+  return lg;
+}
+
+// The compiled tiles (S, NG, occupancy, tile decisions) for this attribute
+// count and chunk (the same table as launch_kc in kc_tighten_impl.h); skip 2
+// is the wide kernel (kc_tighten_wide.h), for NG << lg_kp(k_max) <= 64.
+static std::vector<kc_tile> tighten_variants(int d, int kc, bool single, int k_max) {
   const int D = dsupp(d);
   const int SD = D > 0 && D <= 4 ? 4 : 2;
   const int MD = D > 0 && D * kc <= 6 ? 6 : 0;
@@ -287,12 +294,17 @@ static std::vector<kc_tile> tighten_variants(int d, int kc, bool single) {
     for (int m : {1, 2, 4}) v.push_back({m * SD, 1, 0, 1});
     if (D * kc <= 20)
       for (int m : {1, 2}) v.push_back({m * SD, 2, 0, 1});
+    const int lg = lg_kp(k_max);
+#define KCT_WV(SV, NGV) \
+  if ((NGV << lg) <= 64) v.push_back({SV, NGV, 0, 2});
+    KCT_WIDE_VARIANTS(KCT_WV)
+#undef KCT_WV
   }
   return v;
 }
 
-static bool tile_ok(int d, int kc, bool single, const kc_tile &t) {
-  for (const kc_tile &v : tighten_variants(d, kc, single))
+static bool tile_ok(int d, int kc, bool single, int k_max, const kc_tile &t) {
+  for (const kc_tile &v : tighten_variants(d, kc, single, k_max))
     if (v.S == t.S && v.NG == t.NG && v.bpc == t.bpc && v.skip == t.skip) return true;
   return false;
 }
@@ -328,13 +340,13 @@ static kc_status plan(kc_handle *h, const kc_points *pts, const kc_nodes *nodes,
   const int kc = choose_kc(d, nodes->k_max);
   const int n_chunks = (nodes->k_max + kc - 1) / kc;
   const bool single = n_chunks == 1 && !labels;
-  if (!tile_ok(d, kc, single, t)) t = tighten_variants(d, kc, single)[0];
+  if (!tile_ok(d, kc, single, nodes->k_max, t)) t = tighten_variants(d, kc, single, nodes->k_max)[0];
   const int max_refs = refs ? refs->max_per_box : 0;
   const int node_floats = nodes->k_max * 4 * DM + nodes->k_max * max_refs * DM;
   // dynamic LDS (node slots) plus the kernel's static node table
   size_t lds = (size_t)t.NG * node_floats * 4;
   if (lds + t.NG * sizeof(NodeSlot) > h->lds_per_block && t.NG > 1) {
-    t = tighten_variants(d, kc, single)[0];
+    t = tighten_variants(d, kc, single, nodes->k_max)[0];
     lds = (size_t)node_floats * 4;
   }
   KC_RETURN_IF(lds + t.NG * sizeof(NodeSlot) > h->lds_per_block, h, KC_EUNSUPPORTED,
@@ -374,6 +386,7 @@ static kc_status plan(kc_handle *h, const kc_points *pts, const kc_nodes *nodes,
   A.n_groups = n_groups;
   A.node_floats = node_floats;
   A.span = span;
+  A.lg_kp = lg_kp(nodes->k_max);
   L.kc = kc;
   L.grid = (int)grid;
   L.lds = lds;
@@ -473,7 +486,7 @@ kc_tile kc_tighten_tile(kc_handle *h, const kc_points *pts, const kc_nodes *node
   if (tuned) *tuned = it != h->tune.end();
   if (it != h->tune.end()) return it->second;
   const int kc = choose_kc(pts->d, nodes->k_max);
-  return tighten_variants(pts->d, kc, (nodes->k_max + kc - 1) / kc == 1)[0];
+  return tighten_variants(pts->d, kc, (nodes->k_max + kc - 1) / kc == 1, nodes->k_max)[0];
 }
 
 extern "C" kc_status kc_tighten(kc_handle *h, const kc_points *pts, const kc_nodes *nodes,
@@ -521,10 +534,10 @@ extern "C" kc_status kc_autotune_tighten(kc_handle *h, const kc_points *pts, con
     const int kc = choose_kc(d, nodes->k_max);
     const bool single = (nodes->k_max + kc - 1) / kc == 1;
     double best = 1e30;
-    kc_tile bt = tighten_variants(d, kc, single)[0];
+    kc_tile bt = tighten_variants(d, kc, single, nodes->k_max)[0];
     char key[96];
     tighten_key(key, sizeof(key), d, nodes->k_max, nn, pts->n, refs != nullptr);
-    for (const kc_tile &t : tighten_variants(d, kc, single)) {
+    for (const kc_tile &t : tighten_variants(d, kc, single, nodes->k_max)) {
       Launch L;
       s = plan(h, pts, nodes, alpha, refs, false, t, L);
       if (s != KC_OK) break;

@@ -52,6 +52,7 @@ struct TightenArgs {
   int8_t *labels;
   const uint8_t *light_map;
   int64_t n_lchunks;
+  int lg_kp;  // wide kernel: 2^lg_kp >= k_max lanes per node
 };
 
 constexpr int LCHUNK = 4096;  // samples per chunk of the inside-only decisions
@@ -311,27 +312,13 @@ __device__ __forceinline__ bool tile_node(
   return true;
 }
 
-// D: attribute count (0 = any, up to 16); KC: boxes per chunk held in
-// registers; S: samples per lane per tile; NG: nodes per workgroup; REFS: the
-// batch carries refs (without refs none of that code is compiled in); MINW:
-// wavefronts per SIMD the register allocation must allow (0 = compiler's
-// choice); TSKIP: wavefront tiles that the bounding box of their samples
-// settles skip the per-sample tests (single-chunk launches only).
-template <int D, int KC, int S, int NG, bool REFS, int MINW, bool TSKIP>
-__global__ __launch_bounds__(WG, MINW > 0 ? MINW : 1) void k_tighten(TightenArgs A) {
-  constexpr int DM = D ? D : 16;
-  constexpr int SC = S < 4 ? S : 4;  // samples per chunk of the per-sample path
-  const int dd = D ? D : A.d;
-  extern __shared__ float sm[];  // per node slot: boxes [k_max][2DM], refs' boxes, refs
-  __shared__ NodeSlot s_node[NG];
-
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int u = kcd::xcd_unit(blockIdx.x, gridDim.x);
-  const int chunk = u % A.n_chunks;
-  const int rest = u / A.n_chunks;
-  const int grp = rest % A.n_groups, split = rest / A.n_groups;
-  const int m0 = grp * NG;
-
+// Stages the boxes of nodes m0 .. m0 + NG - 1 in LDS (node slot jn at
+// sm + jn * node_floats: boxes [k_max][2DM], their refs' bounding boxes
+// [k_max][2DM], then the refs), with each box's refs holding the smallest or
+// largest value of some attribute moved to the front. Ends with a barrier.
+template <int DM, int NG, bool REFS>
+__device__ __forceinline__ void stage_nodes(const TightenArgs &A, int m0, NodeSlot *s_node,
+                                            float *sm, int dd, int tid) {
   if (tid < NG) {
     NodeSlot &ns = s_node[tid];
     const int m = m0 + tid;
@@ -431,6 +418,31 @@ __global__ __launch_bounds__(WG, MINW > 0 ? MINW : 1) void k_tighten(TightenArgs
     }
   }
   __syncthreads();
+}
+
+// D: attribute count (0 = any, up to 16); KC: boxes per chunk held in
+// registers; S: samples per lane per tile; NG: nodes per workgroup; REFS: the
+// batch carries refs (without refs none of that code is compiled in); MINW:
+// wavefronts per SIMD the register allocation must allow (0 = compiler's
+// choice); TSKIP: wavefront tiles that the bounding box of their samples
+// settles skip the per-sample tests (single-chunk launches only).
+template <int D, int KC, int S, int NG, bool REFS, int MINW, bool TSKIP>
+__global__ __launch_bounds__(WG, MINW > 0 ? MINW : 1) void k_tighten(TightenArgs A) {
+  constexpr int DM = D ? D : 16;
+  constexpr int SC = S < 4 ? S : 4;  // samples per chunk of the per-sample path
+  const int dd = D ? D : A.d;
+  extern __shared__ float sm[];  // per node slot: boxes [k_max][2DM], refs' boxes, refs
+  __shared__ NodeSlot s_node[NG];
+
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int u = kcd::xcd_unit(blockIdx.x, gridDim.x);
+  const int chunk = u % A.n_chunks;
+  const int rest = u / A.n_chunks;
+  const int grp = rest % A.n_groups, split = rest / A.n_groups;
+  const int m0 = grp * NG;
+
+  stage_nodes<DM, NG, REFS>(A, m0, s_node, sm, dd, tid);
+  const int box_floats = A.k_max * 2 * DM;
 
   const int c0 = chunk * A.kc;
   const bool single = A.n_chunks == 1;
@@ -766,6 +778,10 @@ __global__ __launch_bounds__(WG, MINW > 0 ? MINW : 1) void k_tighten(TightenArgs
 
 }  // namespace kct
 
+// Wide variants (S, NG): usable when NG << lg_kp <= 64.
+#define KCT_WIDE_VARIANTS(X) X(8, 4) X(8, 8) X(8, 16) X(16, 4) X(16, 8) X(16, 16)
+#include "kc_tighten_wide.h"
+
 // Compiled variants per attribute count (the autotuner's table). For KC boxes
 // per chunk: the default tile (S = 4 samples per lane, 16-byte loads, up to 4
 // attributes; 2 beyond), the same held to a register budget of another
@@ -827,6 +843,7 @@ inline bool launch_kc(int S, int NG, int minw, int skip, bool refs, const Tighte
   namespace kct {                                                                       \
   bool NAME(int kc, int S, int NG, int minw, int skip, bool refs, const TightenArgs &A,   \
             int grid, size_t lds, hipStream_t st) {                                     \
+    if (skip == 2) return launch_wide<DV_>(S, NG, refs, A, grid, lds, st);              \
     switch (kc) {                                                                       \
       case 1: return launch_kc<DV_, 1>(S, NG, minw, skip, refs, A, grid, lds, st);      \
       case 2: return launch_kc<DV_, 2>(S, NG, minw, skip, refs, A, grid, lds, st);      \

@@ -620,17 +620,26 @@ def _tighten_tiles(d, k):
         tiles += [(m * sd, 1, 0, 1) for m in (1, 2, 4)]
         if D * kc <= 20:
             tiles += [(m * sd, 2, 0, 1) for m in (1, 2)]
+        # the wide kernel: one (node, box) pair per lane
+        kp = 1
+        while kp < k:
+            kp *= 2
+        tiles += [(S, NG, 0, 2) for S in (8, 16) for NG in (4, 8, 16) if NG * kp <= 64]
     return tiles
 
 
-@pytest.mark.parametrize("seed,n,d,k,nn,with_refs", [
-    (30, 40000, 2, 3, 9, 7), (31, 30001, 2, 3, 5, False), (32, 20000, 4, 5, 7, 3),
-    (33, 15000, 5, 8, 3, 2), (34, 9000, 3, 2, 6, False), (35, 5000, 10, 2, 3, 1)])
-def test_tighten_every_tile_matches_default(kc, tmp_path, seed, n, d, k, nn, with_refs):
+@pytest.mark.parametrize("seed,n,d,k,nn,with_refs,ascale", [
+    (30, 40000, 2, 3, 9, 7, 1.2), (31, 30001, 2, 3, 5, False, 1.2), (32, 20000, 4, 5, 7, 3, 1.2),
+    (33, 15000, 5, 8, 3, 2, 1.2), (34, 9000, 3, 2, 6, False, 1.2), (35, 5000, 10, 2, 3, 1, 1.2),
+    # batches of 8+ nodes without refs: the inside-only kernel takes some
+    # (node, chunk) pairs, every tile the rest
+    (36, 30000, 2, 3, 12, False, 6.0), (37, 20000, 4, 5, 10, False, 3.0),
+    (38, 25000, 2, 3, 17, 4, 0.8)])
+def test_tighten_every_tile_matches_default(kc, tmp_path, seed, n, d, k, nn, with_refs, ascale):
     """Every tile the tightening autotuner can pick (read from a tune cache
     file, one handle per tile) gives the default tile's outputs bit for bit,
     and so does the tile the autotuner picks."""
-    X, off, lo, hi, alpha, ref_off, ref = _tighten_case(seed, n, d, k, nn, with_refs, 1.2, True)
+    X, off, lo, hi, alpha, ref_off, ref = _tighten_case(seed, n, d, k, nn, with_refs, ascale, True)
     xd = kc.to_device_soa(X)
     dev = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a)).cuda()
     args = (xd, n, dev(off), dev(lo), dev(hi), alpha, dev(ref_off), dev(ref))
