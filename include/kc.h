@@ -163,11 +163,15 @@ kc_status kc_objective(kc_handle *h, const kc_points *pts, int32_t n_sets, int32
  * kc_objective(precision = 32) gives; a set with v > cut may stop early and
  * then reports the float32 value of some sample above cut (obj rounded up by
  * the margin from that value, argmax that sample): a lower bound of its
- * objective, above cut. cut = +inf gives kc_objective's results. Same
- * layouts as kc_objective; KC_EINVAL on bad sizes or a NaN cut. */
+ * objective, above cut. cut = +inf gives kc_objective's results. floor
+ * (device, [n_sets], nullable): a lower bound of each set's exact objective
+ * -- for centers inside a node's boxes, the node's lower bound (eqs (8)-(11))
+ * -- which lets whole tiles of samples below it be skipped from the start;
+ * with a valid floor the results are the same. Same layouts as kc_objective;
+ * KC_EINVAL on bad sizes or a NaN cut. */
 kc_status kc_objective_screen(kc_handle *h, const kc_points *pts, int32_t n_sets, int32_t k,
-                              const float *centers, float cut, double *obj, int64_t *argmax,
-                              void *stream);
+                              const float *centers, float cut, const double *floor,
+                              double *obj, int64_t *argmax, void *stream);
 
 /* Algorithm 2 (farthest first traversal) from n_trials starts at once: trial t
  * begins at sample starts[t] and adds, k-1 times, the sample farthest (float64
@@ -351,6 +355,9 @@ typedef struct {
   int32_t sb_nodes;     /* strong-branching nodes labelled                   */
   int64_t node_sr_tries;/* one-node sample reductions run                    */
   int64_t node_sr_kept; /* ... whose sample set a subtree kept               */
+  double obj_kernel_ms; /* total time inside the candidates' float32
+                           objective launches (kc_objective_screen)          */
+  int64_t obj_evals;    /* sample-center evaluations of those launches       */
 } kc_result;
 
 /* Algorithm 1 on the device-resident samples `pts` (synchronous; uses its own

@@ -59,7 +59,8 @@ class Result(C.Structure):
                 ("tighten_kernel_ms", C.c_double), ("tighten_evals", C.c_int64),
                 ("seeds_found", C.c_int32), ("status", C.c_int32), ("sb_rows", C.c_int32),
                 ("sb_nodes", C.c_int32), ("node_sr_tries", C.c_int64),
-                ("node_sr_kept", C.c_int64)]
+                ("node_sr_kept", C.c_int64), ("obj_kernel_ms", C.c_double),
+                ("obj_evals", C.c_int64)]
 
 
 _lib = None
@@ -94,7 +95,7 @@ def load(path: str = LIB_PATH):
     L.kc_objective.argtypes = [vp, P(Points), C.c_int32, C.c_int32, vp, C.c_int32, vp, vp, vp]
     L.kc_objective_screen.restype = st
     L.kc_objective_screen.argtypes = [vp, P(Points), C.c_int32, C.c_int32, vp, C.c_float, vp, vp,
-                                      vp]
+                                      vp, vp]
     L.kc_fft.restype = st
     L.kc_fft.argtypes = [vp, P(Points), C.c_int32, C.c_int32, vp, vp, vp, vp]
     L.kc_tighten.restype = st

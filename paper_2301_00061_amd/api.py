@@ -136,10 +136,12 @@ def objective(x, n, centers: torch.Tensor, precision: int = 32, h: Handle | None
     return obj, am
 
 
-def objective_screen(x, n, centers: torch.Tensor, cut: float, h: Handle | None = None):
+def objective_screen(x, n, centers: torch.Tensor, cut: float, floor=None,
+                     h: Handle | None = None):
     """Float32 eq (12) screened at `cut` (see kc_objective_screen): exact for
     sets at or below the cut; a set above it may report a lower value above
-    the cut. Returns (obj f64, argmax i64)."""
+    the cut. floor (float64 device tensor [n_sets], optional): lower bounds of
+    the sets' objectives. Returns (obj f64, argmax i64)."""
     h = h or handle()
     P = points(x, n)
     centers = centers.contiguous()
@@ -148,8 +150,11 @@ def objective_screen(x, n, centers: torch.Tensor, cut: float, h: Handle | None =
     ns, k = centers.shape[0], centers.shape[1]
     obj = torch.empty(ns, dtype=torch.float64, device=x.device)
     am = torch.empty(ns, dtype=torch.int64, device=x.device)
+    if floor is not None:
+        floor = floor.to(dtype=torch.float64).contiguous()
     h.check(h.lib.kc_objective_screen(h.ptr, C.byref(P), ns, k, _ptr(centers), float(cut),
-                                      _ptr(obj), _ptr(am), _stream()), "kc_objective_screen")
+                                      _ptr(floor), _ptr(obj), _ptr(am), _stream()),
+            "kc_objective_screen")
     return obj, am
 
 
@@ -306,7 +311,8 @@ def solve(x, n, k, batch=64, i_sr=4, use_bt=True, use_seeds=True, max_refs=50, b
                 n_active=r.n_active, seconds=r.seconds, lb_kernel_ms=r.lb_kernel_ms,
                 tighten_kernel_ms=r.tighten_kernel_ms, tighten_evals=r.tighten_evals,
                 seeds_found=bool(r.seeds_found), status=r.status, sb_rows=r.sb_rows,
-                sb_nodes=r.sb_nodes, node_sr_tries=r.node_sr_tries, node_sr_kept=r.node_sr_kept)
+                sb_nodes=r.sb_nodes, node_sr_tries=r.node_sr_tries, node_sr_kept=r.node_sr_kept,
+                obj_kernel_ms=r.obj_kernel_ms, obj_evals=r.obj_evals)
 
 
 class StrongBranchingBuffer:

@@ -154,7 +154,8 @@ extern "C" kc_status kc_create(kc_handle **out, int device, const char *tune_cac
     if (prop.sharedMemPerBlock > 0) h->lds_per_block = prop.sharedMemPerBlock;
     if (h->lds_per_block > 65536) h->lds_per_block = 65536;
   }
-  if (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess) {
+  if (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess ||
+      hipEventCreate(&h->ev2) != hipSuccess || hipEventCreate(&h->ev3) != hipSuccess) {
     kc_destroy(h);
     return KC_EDEVICE;
   }
@@ -183,6 +184,8 @@ extern "C" void kc_destroy(kc_handle *h) {
   }
   if (h->ev0) (void)hipEventDestroy(h->ev0);
   if (h->ev1) (void)hipEventDestroy(h->ev1);
+  if (h->ev2) (void)hipEventDestroy(h->ev2);
+  if (h->ev3) (void)hipEventDestroy(h->ev3);
   delete h;
 }
 

@@ -269,7 +269,7 @@ kc_status kc_launch_bound(kc_handle *h, const kc_points *p, int mode, int n_node
                           int k_max, const int32_t *box_off, const float *lo, const float *hi,
                           float *val_raw, double *val_bound, int64_t *argmax, int64_t *cand,
                           const kc_tile &t0, hipStream_t st, void *fixed_scratch,
-                          size_t fixed_bytes, float cut) {
+                          size_t fixed_bytes, float cut, const double *floor) {
   const bool point = mode == 1;
   const bool with_cand = cand != nullptr && !point;
   kc_tile t = t0;
@@ -339,6 +339,9 @@ kc_status kc_launch_bound(kc_handle *h, const kc_points *p, int mode, int n_node
   A.lg_kp = lg_kp(k_max);
   A.cut = cut;
   A.dead = nullptr;
+  A.floor = point ? floor : nullptr;
+  A.frel = 2.0 * kc_rel_margin(p->d);
+  A.fabs_ = 2.0 * kc_abs_margin(p->d);
   A.gW = A.gC = nullptr;
   if (screen) {
     A.dead = (uint32_t *)scr;
@@ -528,8 +531,9 @@ extern "C" kc_status kc_lower_bound_noalloc(kc_handle *h, const kc_points *pts,
 }
 
 extern "C" kc_status kc_objective_screen(kc_handle *h, const kc_points *pts, int32_t n_sets,
-                                         int32_t k, const float *centers, float cut, double *obj,
-                                         int64_t *argmax, void *stream) {
+                                         int32_t k, const float *centers, float cut,
+                                         const double *floor, double *obj, int64_t *argmax,
+                                         void *stream) {
   return kc_guard(h, [&]() -> kc_status {
     if (!h) return KC_EINVAL;
     kc_status s = kc_validate_points(h, pts);
@@ -541,7 +545,7 @@ extern "C" kc_status kc_objective_screen(kc_handle *h, const kc_points *pts, int
     KC_RETURN_IF(!obj && !argmax, h, KC_EINVAL, "no output requested");
     const kc_tile t = kc_objective_tile(h, pts, n_sets, k, nullptr);
     return kc_launch_bound(h, pts, 1, n_sets, n_sets * k, k, nullptr, centers, centers, nullptr,
-                           obj, argmax, nullptr, t, (hipStream_t)stream, nullptr, 0, cut);
+                           obj, argmax, nullptr, t, (hipStream_t)stream, nullptr, 0, cut, floor);
   });
 }
 

@@ -42,6 +42,11 @@ struct BoundArgs {
   // the cut for set m (read and written by all workgroups).
   float cut;
   uint32_t *dead;
+  // POINT with tile decisions (nullable): a lower bound of each set's exact
+  // objective; lowered by the float32 margin (frel, fabs) it is a value the
+  // set's float32 maximum reaches, so tiles strictly below it are skipped
+  const double *floor;
+  double frel, fabs_;
   // tile decisions: per node the largest W and per box the least cw any
   // wavefront has published (order-preserving encodings; null = no sharing)
   uint32_t *gW, *gC;

@@ -72,6 +72,13 @@ __global__ __launch_bounds__(WG) void k_bound_wide(BoundArgs A) {
   const int cj = lane >> lg, ck = lane & (KP - 1);
   const bool cvalid = cj < NG && m0 + cj < A.n_nodes && ck < s_cnt[cj < NG ? cj : 0];
   float Wl = -1.0f, cwl = INFINITY, Wg = -1.0f, cwg = INFINITY, Wpub = -1.0f, cpub = INFINITY;
+  if (POINT && A.floor && cvalid) {
+    // the set's float32 maximum is at least floor (1 - frel) - fabs
+    const double f = A.floor[m0 + cj] * (1.0 - A.frel) - A.fabs_;
+    float ff = (float)f;
+    if ((double)ff > f) ff = nextafterf(ff, -INFINITY);
+    Wg = fmaxf(Wg, ff);
+  }
   uint64_t deadm = 0;  // screening: bit jn, set jn already exceeds the cut
   uint64_t live = 0;   // bit jn: node jn exists
 #pragma unroll

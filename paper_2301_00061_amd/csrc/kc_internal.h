@@ -38,7 +38,7 @@ struct kc_handle {
   // shape bucket -> chosen tile; transparent comparator, so a lookup by a
   // key in a stack buffer allocates nothing
   std::map<std::string, kc_tile, std::less<>> tune;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr;
   // flags and tile offsets of the last kc_reduce_count, for kc_reduce_compact
   struct {
     const float *x = nullptr;
@@ -80,13 +80,15 @@ kc_status kc_validate_refs(kc_handle *h, const kc_refs *r, const kc_nodes *m);
 // fails with KC_EINVAL and allocates nothing. cut (mode 1 only; +inf = off):
 // a set whose float32 objective exceeds cut may stop early and report the
 // value of some sample above the cut (a lower bound of its objective); sets
-// at or below the cut get their exact value.
+// at or below the cut get their exact value. floor (mode 1, nullable,
+// device [n_nodes]): a lower bound of each set's exact objective, which lets
+// the tile decisions skip tiles below it from the start (results unchanged).
 kc_status kc_launch_bound(kc_handle *h, const kc_points *pts, int mode, int n_nodes,
                           int n_boxes, int k_max, const int32_t *box_off, const float *lo,
                           const float *hi, float *val_raw, double *val_bound, int64_t *argmax,
                           int64_t *cand, const kc_tile &t, hipStream_t st,
                           void *fixed_scratch = nullptr, size_t fixed_bytes = 0,
-                          float cut = INFINITY);
+                          float cut = INFINITY, const double *floor = nullptr);
 // Takes the device address of kc_lower_bound_noalloc's static scratch array
 // for the current device (kc_bound.hip); called by kc_create with h->device
 // current.

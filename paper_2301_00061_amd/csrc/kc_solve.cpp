@@ -1437,25 +1437,37 @@ struct Solver {
       if ((s = kc_gather(h, &p, ids + (size_t)ne * K + i0, (int)gn, ix, dxy + ((size_t)ne * K + i0) * D,
                          orig + (size_t)ne * K + i0, st)))
         return s;
-      // the objective of every candidate set (a set with an empty box reads
-      // sample 0 in its place; its value is never used); over the node's
-      // samples it equals the objective over all samples, since a deleted
-      // sample lies closer than the node's bound to any centers in its boxes
       if (o.autotune) {  // a shape new to the handle's table: sweep the tiles first
         bool tuned = false;
         (void)kc_objective_tile(h, &p, (int)gn, K, &tuned);
         if (!tuned && (s = kc_autotune_objective(h, &p, (int)gn, K, dxy + i0 * K * D, st)))
           return s;
       }
+    }
+    // the objective of every candidate set (a set with an empty box reads
+    // sample 0 in its place; its value is never used); over the node's
+    // samples it equals the objective over all samples, since a deleted
+    // sample lies closer than the node's bound to any centers in its boxes
+    (void)hipEventRecord(h->ev2, st);
+    for (size_t g = 0; g < R.size(); ++g) {
+      const size_t i0 = (size_t)R[g].first, gn = (size_t)(R[g].second - R[g].first);
+      const kc_points p = pts_of(ev[i0]);
+      // each set's centers lie in its node's boxes, so the node's lower
+      // bound is a lower bound of the set's objective
       s = kc_objective_screen(h, &p, (int)gn, K, dxy + i0 * K * D, screen_cut(),
-                              out.dp<double>(o_obj) + i0, out.dp<int64_t>(o_oam) + i0, (void *)st);
+                              out.dp<double>(o_lb) + i0, out.dp<double>(o_obj) + i0,
+                              out.dp<int64_t>(o_oam) + i0, (void *)st);
       if (s) return s;
       res->passes++;
+      res->obj_evals += p.n * (int64_t)gn * K;
     }
+    (void)hipEventRecord(h->ev3, st);
     if ((s = download("bound"))) return s;
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, h->ev0, h->ev1);
     res->lb_kernel_ms += ms;
+    (void)hipEventElapsedTime(&ms, h->ev2, h->ev3);
+    res->obj_kernel_ms += ms;
     const double *lb = out.hp<double>(o_lb);
     const int64_t *cand = out.hp<int64_t>(o_ids);
     const float *xy = out.hp<float>(o_xy);

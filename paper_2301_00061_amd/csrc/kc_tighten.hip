@@ -396,7 +396,9 @@ static kc_status plan(kc_handle *h, const kc_points *pts, const kc_nodes *nodes,
   L.nmax = ni > nodes->n_nodes ? ni : nodes->n_nodes;
   L.t = t;
   // batched launches without refs whose boxes fit one chunk, 1..8 attributes
-  L.inside = !refs && n_chunks == 1 && !labels && d >= 1 && d <= 8 && nodes->n_nodes >= 8;
+  // (the wide kernel settles such tiles itself)
+  L.inside = !refs && n_chunks == 1 && !labels && d >= 1 && d <= 8 && nodes->n_nodes >= 8 &&
+             t.skip != 2;
   L.grid_inside = 0;
   L.cps = 0;
   if (L.inside) {

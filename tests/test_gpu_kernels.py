@@ -793,6 +793,7 @@ def test_objective_screen(kc, tmp_path, n, d, ns, k, seed, ordered):
     C[: ns // 2] = X[near][None] + rng.normal(0, 0.02, (ns // 2, k, d)).astype(np.float32)
     Cd = torch.from_numpy(np.ascontiguousarray(C)).cuda()
     obj_e, am_e = (t.cpu().numpy() for t in kc.objective(xd, n, Cd, precision=32))
+    obj64, _ = oracle.objective(X.astype(np.float64), C.astype(np.float64))
     cut = np.float32(np.median(obj_e))
     below = obj_e <= cut
     above = obj_e > float(cut) * 1.001
@@ -811,6 +812,11 @@ def test_objective_screen(kc, tmp_path, n, d, ns, k, seed, ordered):
             h = kc.Handle(0, str(path))
         o_inf, a_inf = (t.cpu().numpy() for t in kc.objective_screen(xd, n, Cd, float("inf"), h=h))
         assert np.array_equal(o_inf, obj_e) and np.array_equal(a_inf, am_e), tile
+        # lower bounds of the objectives (the exact one, and below it) change nothing
+        for fl in (obj64, 0.9 * obj64):
+            o_f, a_f = (t.cpu().numpy() for t in
+                        kc.objective_screen(xd, n, Cd, float("inf"), floor=torch.from_numpy(fl).cuda(), h=h))
+            assert np.array_equal(o_f, obj_e) and np.array_equal(a_f, am_e), (tile, "floor")
         o_s, a_s = (t.cpu().numpy() for t in kc.objective_screen(xd, n, Cd, float(cut), h=h))
         if h is not None:
             h.close()
