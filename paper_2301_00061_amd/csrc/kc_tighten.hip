@@ -114,54 +114,77 @@ __global__ __launch_bounds__(256) void k_chunk_bbox(const float *x, int64_t n, i
   }
 }
 
-// One node and one split of whole chunks per workgroup: per chunk, the
-// decision from its bounding box, then (when it holds) per lane the count and
-// bounding box of its samples inside each box.
-template <int D, int KC, int S>
+// NG nodes and one split of whole chunks per workgroup: per chunk, each
+// node's decision from the chunk's bounding box; when it holds for some node,
+// the chunk's samples are read once and, per lane, the count and bounding box
+// of its samples inside each box of those nodes are folded.
+template <int D, int KC, int S, int NG>
 __global__ __launch_bounds__(WG) void k_tighten_inside(TightenArgs A, const float *cbb,
                                                        uint8_t *map, int64_t chunks_per_split) {
-  __shared__ float sb[KC][2][D];
+  __shared__ float sb[NG][KC][2][D];
+  __shared__ int s_b0[NG], s_cnt[NG];
   const int tid = threadIdx.x, lane = tid & 63;
   const int u = kcd::xcd_unit(blockIdx.x, gridDim.x);
-  const int m = u % A.n_nodes, split = u / A.n_nodes;
-  const int b0 = kcd::clampi(A.box_off[m], 0, A.n_boxes);
-  const int b1 = kcd::clampi(A.box_off[m + 1], b0, A.n_boxes);
-  const int cnt = min(min(b1 - b0, A.k_max), KC);
-  for (int i = tid; i < KC * D; i += WG) {
-    const int k = i / D, a = i - k * D;
-    sb[k][0][a] = k < cnt ? A.lo[(int64_t)(b0 + k) * D + a] : 0.f;
-    sb[k][1][a] = k < cnt ? A.hi[(int64_t)(b0 + k) * D + a] : 0.f;
+  const int n_groups = (A.n_nodes + NG - 1) / NG;
+  const int grp = u % n_groups, split = u / n_groups;
+  const int m0 = grp * NG;
+  if (tid < NG) {
+    const int m = m0 + tid;
+    int b0 = 0, c = 0;
+    if (m < A.n_nodes) {
+      b0 = kcd::clampi(A.box_off[m], 0, A.n_boxes);
+      const int b1 = kcd::clampi(A.box_off[m + 1], b0, A.n_boxes);
+      c = min(min(b1 - b0, A.k_max), KC);
+    }
+    s_b0[tid] = b0;
+    s_cnt[tid] = c;
   }
   __syncthreads();
-  float bmin[KC][D], bmax[KC][D];
-  uint32_t nin[KC];
-#pragma unroll
-  for (int k = 0; k < KC; ++k) {
-    nin[k] = 0;
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-      bmin[k][a] = INFINITY;
-      bmax[k][a] = -INFINITY;
-    }
+  for (int i = tid; i < NG * KC * D; i += WG) {
+    const int jn = i / (KC * D), r = i - jn * KC * D;
+    const int k = r / D, a = r - k * D;
+    const bool ok = k < s_cnt[jn];
+    sb[jn][k][0][a] = ok ? A.lo[(int64_t)(s_b0[jn] + k) * D + a] : 0.f;
+    sb[jn][k][1][a] = ok ? A.hi[(int64_t)(s_b0[jn] + k) * D + a] : 0.f;
   }
+  __syncthreads();
+  float bmin[NG][KC][D], bmax[NG][KC][D];
+  uint32_t nin[NG][KC];
+#pragma unroll
+  for (int jn = 0; jn < NG; ++jn)
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+      nin[jn][k] = 0;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        bmin[jn][k][a] = INFINITY;
+        bmax[jn][k][a] = -INFINITY;
+      }
+    }
   const int64_t cb0 = (int64_t)split * chunks_per_split;
   const int64_t cb1 = min(A.n_lchunks, cb0 + chunks_per_split);
   for (int64_t c = cb0; c < cb1; ++c) {
-    // the chunk's decision (uniform): every box's center-based bound over the
-    // chunk's bounding box within alpha
-    bool light = cnt >= 2;
-    for (int k = 0; k < cnt && light; ++k) {
-      float ub = 0.f;
+    // each node's decision for the chunk (uniform): every box's center-based
+    // bound over the chunk's bounding box within alpha
+    uint32_t lightm = 0;
 #pragma unroll
-      for (int a = 0; a < D; ++a) {
-        const float blo = cbb[(c * 2) * D + a], bhi = cbb[(c * 2 + 1) * D + a];
-        const float uu = fmaxf(fmaxf(sb[k][0][a] - blo, bhi - sb[k][1][a]), 0.f);
-        ub = (a == 0) ? uu * uu : __builtin_fmaf(uu, uu, ub);
+    for (int jn = 0; jn < NG; ++jn) {
+      const int cnt = s_cnt[jn];
+      bool light = m0 + jn < A.n_nodes && cnt >= 2;
+      for (int k = 0; k < cnt && light; ++k) {
+        float ub = 0.f;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          const float blo = cbb[(c * 2) * D + a], bhi = cbb[(c * 2 + 1) * D + a];
+          const float uu = fmaxf(fmaxf(sb[jn][k][0][a] - blo, bhi - sb[jn][k][1][a]), 0.f);
+          ub = (a == 0) ? uu * uu : __builtin_fmaf(uu, uu, ub);
+        }
+        light = !(ub > A.t_center);
       }
-      light = !(ub > A.t_center);
+      if (tid == 0 && m0 + jn < A.n_nodes) map[(int64_t)(m0 + jn) * A.n_lchunks + c] = light ? 1 : 0;
+      if (light) lightm |= 1u << jn;
     }
-    if (tid == 0) map[(int64_t)m * A.n_lchunks + c] = light ? 1 : 0;
-    if (!light) continue;
+    if (!lightm) continue;
     const int64_t s_hi = min(A.n, (c + 1) * (int64_t)LCHUNK);
     for (int64_t base = c * (int64_t)LCHUNK + (int64_t)tid * S; base < s_hi;
          base += (int64_t)WG * S) {
@@ -186,25 +209,30 @@ __global__ __launch_bounds__(WG) void k_tighten_inside(TightenArgs A, const floa
         }
       }
 #pragma unroll
-      for (int k = 0; k < KC; ++k) {
-        if (k >= cnt) break;
-        float l[D], h[D];
+      for (int jn = 0; jn < NG; ++jn) {
+        if (!((lightm >> jn) & 1u)) continue;
+        const int cnt = s_cnt[jn];
 #pragma unroll
-        for (int a = 0; a < D; ++a) {
-          l[a] = sb[k][0][a];
-          h[a] = sb[k][1][a];
-        }
+        for (int k = 0; k < KC; ++k) {
+          if (k >= cnt) break;
+          float l[D], h[D];
 #pragma unroll
-        for (int i = 0; i < S; ++i) {
-          bool in = base + i < s_hi;
+          for (int a = 0; a < D; ++a) {
+            l[a] = sb[jn][k][0][a];
+            h[a] = sb[jn][k][1][a];
+          }
 #pragma unroll
-          for (int a = 0; a < D; ++a) in = in && l[a] <= xs[i][a] && xs[i][a] <= h[a];
-          if (in) {
-            ++nin[k];
+          for (int i = 0; i < S; ++i) {
+            bool in = base + i < s_hi;
 #pragma unroll
-            for (int a = 0; a < D; ++a) {
-              bmin[k][a] = fminf(bmin[k][a], xs[i][a]);
-              bmax[k][a] = fmaxf(bmax[k][a], xs[i][a]);
+            for (int a = 0; a < D; ++a) in = in && l[a] <= xs[i][a] && xs[i][a] <= h[a];
+            if (in) {
+              ++nin[jn][k];
+#pragma unroll
+              for (int a = 0; a < D; ++a) {
+                bmin[jn][k][a] = fminf(bmin[jn][k][a], xs[i][a]);
+                bmax[jn][k][a] = fmaxf(bmax[jn][k][a], xs[i][a]);
+              }
             }
           }
         }
@@ -212,28 +240,49 @@ __global__ __launch_bounds__(WG) void k_tighten_inside(TightenArgs A, const floa
     }
   }
 #pragma unroll
-  for (int k = 0; k < KC; ++k) {
-    const uint32_t ci = kcd::wave_sum_u32(nin[k]);
+  for (int jn = 0; jn < NG; ++jn) {
+    const int cnt = m0 + jn < A.n_nodes ? s_cnt[jn] : 0;
+    const int b0 = s_b0[jn];
 #pragma unroll
-    for (int a = 0; a < D; ++a) {
-      const uint32_t v0 = kcd::wave_min_u32(kcd::ford(bmin[k][a]));
-      const uint32_t v1 = kcd::wave_max_u32(kcd::ford(bmax[k][a]));
-      if (lane == 0 && k < cnt && ci) {
-        const int64_t o = (int64_t)(b0 + k) * D + a;
-        atomicMin(&A.bb_lo[o], v0);
-        atomicMax(&A.bb_hi[o], v1);
+    for (int k = 0; k < KC; ++k) {
+      const uint32_t ci = kcd::wave_sum_u32(nin[jn][k]);
+      if (!ci) continue;  // uniform
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        const uint32_t v0 = kcd::wave_min_u32(kcd::ford(bmin[jn][k][a]));
+        const uint32_t v1 = kcd::wave_max_u32(kcd::ford(bmax[jn][k][a]));
+        if (lane == 0 && k < cnt) {
+          const int64_t o = (int64_t)(b0 + k) * D + a;
+          atomicMin(&A.bb_lo[o], v0);
+          atomicMax(&A.bb_hi[o], v1);
+        }
       }
+      if (lane == 0 && k < cnt) atomicAdd(&A.n_in[b0 + k], ci);
     }
-    if (lane == 0 && k < cnt && ci) atomicAdd(&A.n_in[b0 + k], ci);
   }
+}
+
+// Nodes per workgroup of the inside-only kernel: as many as keep its
+// per-lane aggregates within about 96 registers.
+static int inside_ng(int d, int kc) {
+  const int per = 2 * kc * d + kc;
+  return per * 4 <= 96 ? 4 : (per * 2 <= 96 ? 2 : 1);
 }
 
 template <int D>
 static bool launch_inside_d(int kc, const TightenArgs &A, const float *cbb, uint8_t *map,
                             int64_t cps, int grid, hipStream_t st) {
   constexpr int S = D <= 4 ? 4 : 2;
-#define KCT_IN(KV) \
-  case KV: k_tighten_inside<D, KV, S><<<grid, WG, 0, st>>>(A, cbb, map, cps); return true;
+  const int ng = inside_ng(D, kc);
+#define KCT_IN(KV)                                                                      \
+  case KV:                                                                              \
+    if (ng == 4)                                                                        \
+      k_tighten_inside<D, KV, S, 4><<<grid, WG, 0, st>>>(A, cbb, map, cps);              \
+    else if (ng == 2)                                                                   \
+      k_tighten_inside<D, KV, S, 2><<<grid, WG, 0, st>>>(A, cbb, map, cps);              \
+    else                                                                                \
+      k_tighten_inside<D, KV, S, 1><<<grid, WG, 0, st>>>(A, cbb, map, cps);              \
+    return true;
   switch (kc) {
     KCT_IN(1) KCT_IN(2) KCT_IN(3) KCT_IN(4) KCT_IN(5) KCT_IN(6) KCT_IN(8)
     default: return false;
@@ -403,11 +452,13 @@ static kc_status plan(kc_handle *h, const kc_points *pts, const kc_nodes *nodes,
   L.cps = 0;
   if (L.inside) {
     const int64_t nch = (pts->n + LCHUNK - 1) / LCHUNK;
-    int64_t sp = (target + nodes->n_nodes - 1) / nodes->n_nodes;
+    const int ng = inside_ng(d, kc);
+    const int64_t groups = (nodes->n_nodes + ng - 1) / ng;
+    int64_t sp = (target + groups - 1) / groups;
     L.cps = (nch + sp - 1) / sp;
     sp = (nch + L.cps - 1) / L.cps;
-    L.inside = sp * nodes->n_nodes <= 0x7fffffff;
-    L.grid_inside = (int)(sp * nodes->n_nodes);
+    L.inside = sp * groups <= 0x7fffffff;
+    L.grid_inside = (int)(sp * groups);
     L.n_lchunks = nch;
   }
   return KC_OK;
