@@ -167,7 +167,9 @@ kc_status kc_objective(kc_handle *h, const kc_points *pts, int32_t n_sets, int32
  * (device, [n_sets], nullable): a lower bound of each set's exact objective
  * -- for centers inside a node's boxes, the node's lower bound (eqs (8)-(11))
  * -- which lets whole tiles of samples below it be skipped from the start;
- * with a valid floor the results are the same. Same layouts as kc_objective;
+ * with a valid floor the results are the same, except that a set whose floor
+ * (lowered by the float32 margin) already exceeds cut is not evaluated: it
+ * reports that lowered floor, with argmax -1. Same layouts as kc_objective;
  * KC_EINVAL on bad sizes or a NaN cut. */
 kc_status kc_objective_screen(kc_handle *h, const kc_points *pts, int32_t n_sets, int32_t k,
                               const float *centers, float cut, const double *floor,

@@ -78,7 +78,8 @@ __global__ __launch_bounds__(64) void k_bound_finalize(
     const float v = key ? __uint_as_float((uint32_t)(key >> 32)) : 0.0f;
     const uint32_t idx = key ? ~(uint32_t)(key & 0xffffffffu) : 0u;
     if (val_raw) val_raw[b] = v;
-    if (argmax) argmax[b] = (int64_t)idx;
+    // index 0xffffffff: a screened set settled by its floor alone (no sample)
+    if (argmax) argmax[b] = idx == 0xffffffffu ? -1 : (int64_t)idx;
     if (val_bound) {
       const double vd = (double)v;
       double r;

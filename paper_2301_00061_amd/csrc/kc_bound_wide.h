@@ -43,10 +43,27 @@ __global__ __launch_bounds__(WG) void k_bound_wide(BoundArgs A) {
     s_beg[tid] = b0;
     s_cnt[tid] = c;
   }
+  __shared__ int s_dead0[NG];
   for (int i = tid; i < NWAVE * NG; i += WG) s_key[i / NG][i % NG] = 0ull;
   if constexpr (KC > 0)
     for (int i = tid; i < NWAVE * NG * KC; i += WG) s_cand[i / (NG * KC)][i % (NG * KC)] = ~0ull;
   __syncthreads();
+  if (tid < NG) {
+    // screening with a floor above the cut: the set cannot improve the
+    // incumbent, and the lowered floor is a value it reaches -- reported
+    // with no sample (index 0xffffffff), no tile evaluated
+    int dead0 = 0;
+    if (POINT && A.floor && A.dead && m0 + tid < A.n_nodes) {
+      const double f = A.floor[m0 + tid] * (1.0 - A.frel) - A.fabs_;
+      float ff = (float)f;
+      if ((double)ff > f) ff = nextafterf(ff, -INFINITY);
+      if (ff > A.cut) {
+        dead0 = 1;
+        if (split == 0) s_key[0][tid] = kcd::key_max(ff, 0xffffffffu);
+      }
+    }
+    s_dead0[tid] = dead0;
+  }
   const int per_node = A.k_max * 2 * DM;
   for (int i = tid; i < NG * A.k_max * DM; i += WG) {
     const int jn = i / (A.k_max * DM);
@@ -79,7 +96,7 @@ __global__ __launch_bounds__(WG) void k_bound_wide(BoundArgs A) {
     if ((double)ff > f) ff = nextafterf(ff, -INFINITY);
     Wg = fmaxf(Wg, ff);
   }
-  uint64_t deadm = 0;  // screening: bit jn, set jn already exceeds the cut
+  uint64_t deadm = __ballot(lane < NG && s_dead0[lane < NG ? lane : 0] != 0);  // screening
   uint64_t live = 0;   // bit jn: node jn exists
 #pragma unroll
   for (int jn = 0; jn < NG; ++jn)

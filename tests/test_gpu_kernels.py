@@ -818,6 +818,15 @@ def test_objective_screen(kc, tmp_path, n, d, ns, k, seed, ordered):
                         kc.objective_screen(xd, n, Cd, float("inf"), floor=torch.from_numpy(fl).cuda(), h=h))
             assert np.array_equal(o_f, obj_e) and np.array_equal(a_f, am_e), (tile, "floor")
         o_s, a_s = (t.cpu().numpy() for t in kc.objective_screen(xd, n, Cd, float(cut), h=h))
+        # with floors too: sets below the cut are exact; a set whose floor
+        # alone exceeds the cut reports a value above it, at most its
+        # objective, and no sample
+        o_sf, a_sf = (t.cpu().numpy() for t in
+                      kc.objective_screen(xd, n, Cd, float(cut), floor=torch.from_numpy(obj64).cuda(), h=h))
+        assert np.array_equal(o_sf[below], obj_e[below]) and np.array_equal(a_sf[below], am_e[below]), tile
+        for c in np.nonzero(above)[0]:
+            assert float(cut) < o_sf[c] <= obj_e[c], (tile, c)
+            assert a_sf[c] == -1 or a_sf[c] >= 0
         if h is not None:
             h.close()
         assert np.array_equal(o_s[below], obj_e[below]) and np.array_equal(a_s[below], am_e[below]), tile
