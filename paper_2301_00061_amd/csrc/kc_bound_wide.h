@@ -106,11 +106,8 @@ __global__ __launch_bounds__(WG) void k_bound_wide(BoundArgs A) {
   const int64_t s_lo = (int64_t)split * A.span;
   const int64_t s_hi = min(A.n, s_lo + A.span);
   const int64_t lane_off = (int64_t)tid * S;
-  for (int64_t base = s_lo + lane_off; base - lane_off < s_hi; base += (int64_t)WG * S) {
-    const bool refresh = (tick++ & 15) == 0;
-    const int64_t wb = base - lane_off + (int64_t)wave * 64 * S;
-    if (wb >= s_hi) continue;  // no sample of this wavefront lies in the split (uniform)
-    float xv[DM][S];
+  // a lane's S consecutive samples from base (zeros past the split's end)
+  auto load = [&](float (&xv)[DM][S], int64_t base) {
     const bool full = base + S <= s_hi;
 #pragma unroll
     for (int a = 0; a < DM; ++a) {
@@ -138,6 +135,21 @@ __global__ __launch_bounds__(WG) void k_bound_wide(BoundArgs A) {
         for (int i = 0; i < S; ++i) xv[a][i] = (base + i < s_hi) ? p[i] : 0.0f;
       }
     }
+  };
+  // the next tile's samples are requested before the current tile is
+  // processed, so their latency overlaps its decisions and evaluations
+  float xn[DM][S];
+  if (s_lo < s_hi) load(xn, s_lo + lane_off);
+  for (int64_t base = s_lo + lane_off; base - lane_off < s_hi; base += (int64_t)WG * S) {
+    float xv[DM][S];
+#pragma unroll
+    for (int a = 0; a < DM; ++a)
+#pragma unroll
+      for (int i = 0; i < S; ++i) xv[a][i] = xn[a][i];
+    if (base - lane_off + (int64_t)WG * S < s_hi) load(xn, base + (int64_t)WG * S);
+    const bool refresh = (tick++ & 15) == 0;
+    const int64_t wb = base - lane_off + (int64_t)wave * 64 * S;
+    if (wb >= s_hi) continue;  // no sample of this wavefront lies in the split (uniform)
     float tlo[DM], thi[DM];
 #pragma unroll
     for (int a = 0; a < DM; ++a) {
@@ -221,10 +233,8 @@ __global__ __launch_bounds__(WG) void k_bound_wide(BoundArgs A) {
         if (ia) cwl = fminf(cwl, um);
       }
     }
-    for (int o = 1; o < KP; o <<= 1) {
-      lbk = fminf(lbk, __shfl_xor(lbk, o));
-      ubk = fminf(ubk, __shfl_xor(ubk, o));
-    }
+    lbk = kcd::group_min(lbk, KP);
+    ubk = kcd::group_min(ubk, KP);
     bool ns = ubk <= Wl || ubk < Wg;
     Wl = fmaxf(Wl, lbk);
     if constexpr (KC > 0) {

@@ -162,10 +162,8 @@ __device__ __forceinline__ void classify_nodes(const FlagArgs &A, int g0, int lg
     }
   }
   // node-wide values: minimum over the node's lanes; AND / OR of the flags
-  for (int o = 1; o < KP; o <<= 1) {
-    alo = fminf(alo, __shfl_xor(alo, o));
-    ahi = fminf(ahi, __shfl_xor(ahi, o));
-  }
+  alo = kcd::group_min(alo, KP);
+  ahi = kcd::group_min(ahi, KP);
   const uint64_t seg = KP >= 64 ? ~0ull : ((1ull << KP) - 1ull);
   const uint64_t b_nall = __ballot(!ub_all), b_none = __ballot(ub_none);
   const int sh = jn << lg;

@@ -9,8 +9,10 @@
 // launched together); each surviving node is split (max-range rule of Section 3.3, or the learned
 // rule) and one kc_lower_bound launch bounds all children and returns their
 // Section 3.2 candidates; one kc_objective launch screens the candidates in
-// float32 (rounded up); an improvement is certified in float64 over the
-// original samples. Nodes are pruned when their rigorous lower bound reaches
+// float32 (rounded up), and the best set's rigorous float32 bound becomes the
+// incumbent bound that prunes; its float64 objective over the original
+// samples is taken once, when the search ends (a later improvement always
+// beats an earlier one, so only the last needs it). Nodes are pruned when their rigorous lower bound reaches
 // the incumbent, and every node that leaves the tree records the bound it
 // leaves behind, so the final lower bound is rigorous too.
 //
@@ -18,7 +20,7 @@
 // download through a pinned staging arena; the coordinates of candidates and
 // new refs are gathered on the device, so a pass synchronises twice (after
 // the tightening phase and after the bounding phase), plus once for a
-// certificate or a sample reduction.
+// sample reduction.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -194,6 +196,10 @@ struct Solver {
   double alpha_ub = INFINITY;     // valid upper bound used for pruning
   std::vector<int64_t> inc_ids;
   std::vector<float> inc_coords;
+  // best set found since the last certificate (alpha_ub bounds its objective)
+  bool pending = false;
+  std::vector<int64_t> pend_ids;
+  std::vector<float> pend_coords;
   double lb_closed = INFINITY;    // least bound among nodes that left the tree
 
   // root data
@@ -252,6 +258,33 @@ struct Solver {
   }
 
   double prune_thr() const { return alpha_ub * (1.0 - o.eps_rel); }
+
+  // Float64 objective over the original samples of the pending set: it
+  // becomes the incumbent if it beats the certified one (it always does,
+  // since its rigorous float32 bound was below every earlier bound).
+  kc_status certify() {
+    if (!pending) return KC_OK;
+    pending = false;
+    in.reset();
+    out.reset();
+    const size_t o_c = in.take((size_t)K * D * 4), o_v = out.take(8);
+    kc_status s = reserve();
+    if (s) return s;
+    std::memcpy(in.hp<float>(o_c), pend_coords.data(), (size_t)K * D * 4);
+    if ((s = upload())) return s;
+    if ((s = kc_objective(h, X0, 1, K, in.dp<float>(o_c), 64, out.dp<double>(o_v), nullptr, st)))
+      return s;
+    res->passes++;
+    if ((s = download("certificate"))) return s;
+    const double cert = *out.hp<double>(o_v);
+    if (cert < alpha_cert) {
+      alpha_cert = cert;
+      inc_ids = pend_ids;
+      inc_coords = pend_coords;
+    }
+    alpha_ub = std::min(alpha_ub, alpha_cert);
+    return KC_OK;
+  }
   // Screening threshold of the candidates' float32 objective: a set whose
   // value v exceeds it has v (1 + rel) + eta > alpha_ub, so it cannot become
   // the incumbent, and its launch may stop early (reporting the value of some
@@ -1351,13 +1384,15 @@ struct Solver {
 
       if (!heap.empty()) {
         const double lb = global_lb();
-        if (alpha_cert - lb <= o.eps_rel * alpha_cert) break;
+        // alpha_ub bounds the best set's objective from above, so the gap
+        // after its certificate is no larger
+        if (alpha_ub - lb <= o.eps_rel * alpha_ub) break;
       }
       if (o.verbose && (res->nodes % (o.batch * 20) < o.batch))
         fprintf(stderr,
                 "[kc_solve] nodes %lld open %zu n_active %lld subtree sets %.3f GB alpha %.9g lb %.9g "
                 "t %.2fs\n",
-                (long long)res->nodes, heap.size(), (long long)act.n, set_bytes * 1e-9, alpha_cert,
+                (long long)res->nodes, heap.size(), (long long)act.n, set_bytes * 1e-9, alpha_ub,
                 global_lb(), now_s() - t0);
     }
     if (o.verbose)
@@ -1401,7 +1436,7 @@ struct Solver {
     const size_t o_lb = out.take((size_t)ne * 8), o_ids = out.take(ng * 8),
                  o_xy = out.take(ng * D * 4), o_orig = out.take(ng * 8),
                  o_obj = out.take((size_t)ne * 8), o_oam = out.take((size_t)ne * 8),
-                 o_cert = out.take(8), o_cam = out.take(8), o_l64 = out.take((size_t)ne * 8);
+                 o_l64 = out.take((size_t)ne * 8);
     kc_status s = reserve();
     if (s) return s;
     for (size_t g = 0; g < R.size(); ++g) fill_boxes(plans[g], glo[g], ghi[g], nullptr);
@@ -1481,23 +1516,11 @@ struct Solver {
         if (cand[(size_t)i * K + k] < 0) ok[i] = 0;  // no sample in some box
       if (ok[i] && ub[i] < alpha_ub && (best < 0 || ub[i] < ub[best])) best = i;
     }
-    if (best >= 0) {
+    if (best >= 0) {  // the new incumbent bound; certified when the search ends
       alpha_ub = ub[best];
-      // certify in float64 over the original samples
-      if ((s = kc_objective(h, X0, 1, K, out.dp<float>(o_xy) + (size_t)best * K * D, 64,
-                            out.dp<double>(o_cert), out.dp<int64_t>(o_cam), st)))
-        return s;
-      res->passes++;
-      double cert = 0.0;
-      if (hipMemcpyAsync(&cert, out.dp<double>(o_cert), 8, hipMemcpyDeviceToHost, st) != hipSuccess)
-        return kc_fail(h, KC_EDEVICE, "download");
-      if ((s = sync("certificate"))) return s;
-      if (cert < alpha_cert) {
-        alpha_cert = cert;
-        inc_ids.assign(horig + (size_t)best * K, horig + (size_t)best * K + K);
-        inc_coords.assign(xy + (size_t)best * K * D, xy + (size_t)best * K * D + K * D);
-      }
-      alpha_ub = std::min(alpha_ub, alpha_cert);
+      pending = true;
+      pend_ids.assign(horig + (size_t)best * K, horig + (size_t)best * K + K);
+      pend_coords.assign(xy + (size_t)best * K * D, xy + (size_t)best * K * D + K * D);
     }
     const double thr = prune_thr();
     const double rel = kc_rel_margin(D) + 0x1p-50, eta = kc_abs_margin(D);
@@ -1517,7 +1540,7 @@ struct Solver {
       for (int i = 0; i < ne; ++i) {
         if (!is_leaf[i] || !ok[i]) continue;
         const double lo_obj = std::max(0.0, (ub[i] - eta) / (1.0 + rel) * (1.0 - rel) - eta);
-        if (std::max(ev[i]->lb, lo_obj) < alpha_cert * (1.0 - o.eps_rel)) band.push_back(i);
+        if (std::max(ev[i]->lb, lo_obj) < alpha_ub * (1.0 - o.eps_rel)) band.push_back(i);
       }
       if (!band.empty()) {
         double *d64 = out.dp<double>(o_l64), *h64 = out.hp<double>(o_l64);
@@ -1589,6 +1612,7 @@ extern "C" kc_status kc_solve(kc_handle *h, const kc_points *pts, const kc_opts 
     Solver S(h, pts, opts, res);
     const double t0 = now_s();
     s = S.run();
+    if (s == KC_OK) s = S.certify();
     if (s != KC_OK) {
       (void)hipDeviceSynchronize();
       return s;
