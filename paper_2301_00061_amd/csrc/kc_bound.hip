@@ -178,9 +178,15 @@ std::vector<kc_tile> kc_bound_variants(int d, bool with_cand, int k_max) {
     KCB_LB_TS_VARIANTS(KCB_T2S)
 #undef KCB_T2S
   }
-  // each shape at two occupancies
+  // each shape at two occupancies; the tile-decision kernels also with
+  // smaller splits (more workgroups), since their work per split is uneven
   const size_t n0 = v.size();
   for (size_t i = 0; i < n0; ++i) v.push_back({v[i].S, v[i].NG, 4, v[i].skip});
+  for (size_t i = 0; i < n0; ++i)
+    if (v[i].skip) {
+      v.push_back({v[i].S, v[i].NG, 16, 1});
+      v.push_back({v[i].S, v[i].NG, 32, 1});
+    }
   return v;
 }
 
@@ -419,8 +425,12 @@ kc_status kc_autotune_objective(kc_handle *h, const kc_points *p, int n_sets, in
   KCB_PT_VARIANTS(KCB_T6)
 #undef KCB_T6
   if (p->d >= 1 && p->d <= 8) {
-#define KCB_T6S(SV, NGV) \
-  if (ts_fits(NGV, k)) vars.push_back({SV, NGV, 8, 1});
+#define KCB_T6S(SV, NGV)                \
+  if (ts_fits(NGV, k)) {                \
+    vars.push_back({SV, NGV, 8, 1});    \
+    vars.push_back({SV, NGV, 16, 1});   \
+    vars.push_back({SV, NGV, 32, 1});   \
+  }
     KCB_PT_TS_VARIANTS(KCB_T6S)
 #undef KCB_T6S
   }

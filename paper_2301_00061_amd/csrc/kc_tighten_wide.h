@@ -15,8 +15,10 @@
 
 namespace kct {
 
-template <int D, int S, int NG, bool REFS>
-__global__ __launch_bounds__(WG) void k_tighten_wide(TightenArgs A) {
+// CAP: registers limited to four wavefronts per SIMD (a grid of four
+// workgroups per compute unit is then resident at once)
+template <int D, int S, int NG, bool REFS, bool CAP>
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(CAP ? 4 : 1))) void k_tighten_wide(TightenArgs A) {
   static_assert(D >= 1 && D <= 8, "tile decisions are compiled for 1..8 attributes");
   constexpr int DM = D;
   extern __shared__ float sm[];  // per node slot: boxes [k_max][2DM], refs' boxes, refs
@@ -115,6 +117,11 @@ __global__ __launch_bounds__(WG) void k_tighten_wide(TightenArgs A) {
     // some ref (far), and likewise for alpha (the balls of S_+).
     bool c_out = false, c_keep = false, in_all = false, in_none = true;
     bool near_all = true, near_none = false, ball_all = true, ball_none = false;
+    // whether a sample of the tile can change the box's aggregates as this
+    // wavefront holds them: the assigned and S_+ bounding boxes (a value
+    // inside both ends changes neither), the farthest assigned sample (a tile
+    // wholly nearer the midpoint than a folded one cannot hold it)
+    bool a_chg = false, b_chg = false, f_chg = false;
     float lm = 0.f, um = 0.f;
     if (cvalid) {
       float lb = 0.f, ub = 0.f;
@@ -137,6 +144,12 @@ __global__ __launch_bounds__(WG) void k_tighten_wide(TightenArgs A) {
       }
       c_out = lb > A.t_center;
       c_keep = !(ub > A.t_center);
+#pragma unroll
+      for (int a = 0; a < DM; ++a) {
+        a_chg = a_chg || tlo[a] < amin[a] || thi[a] > amax[a];
+        b_chg = b_chg || tlo[a] < bmin[a] || thi[a] > bmax[a];
+      }
+      f_chg = !(um < fw);
       if (REFS && crc > 0) {
         // the refs' bounding box settles most tiles; else each ref
         float bn = 0.f, bx = 0.f;
@@ -174,6 +187,7 @@ __global__ __launch_bounds__(WG) void k_tighten_wide(TightenArgs A) {
       }
     }
     const uint64_t b_out = __ballot(c_out), b_keep = __ballot(c_keep);
+    const uint64_t b_achg = __ballot(a_chg), b_bchg = __ballot(b_chg), b_fchg = __ballot(f_chg);
     const uint64_t b_near = __ballot(near_all), b_nnone = __ballot(near_none);
 
     // The node's label over the tile (as the per-sample rule: every box but
@@ -325,11 +339,17 @@ __global__ __launch_bounds__(WG) void k_tighten_wide(TightenArgs A) {
             const uint64_t kk = kcd::key_max(dm, (uint32_t)(base + i));
             key = kk > key ? kk : key;
           }
-          key = kcd::wave_max_u64(key);
-          if (owner) far = key > far ? key : far;
+          if (fo || ((b_fchg >> bit) & 1ull)) {
+            key = kcd::wave_max_u64(key);
+            if (owner) {
+              far = key > far ? key : far;
+              if (key) fw = fmaxf(fw, __uint_as_float((uint32_t)(key >> 32)));
+            }
+          }
           if (unset) {
             const uint32_t cs = kcd::wave_sum_u32(c);
             if (owner) nasg += cs;
+            if (cs && ((b_achg >> bit) & 1ull))
 #pragma unroll
             for (int a = 0; a < DM; ++a) {
               const float v0 = kcd::fdec(kcd::wave_min_u32(kcd::ford(mn[a])));
@@ -371,7 +391,7 @@ __global__ __launch_bounds__(WG) void k_tighten_wide(TightenArgs A) {
           }
           const uint32_t cs = kcd::wave_sum_u32(c);
           if (owner) nin += cs;
-          if (cs) {
+          if (cs && ((b_bchg >> bit) & 1ull)) {
 #pragma unroll
             for (int a = 0; a < DM; ++a) {
               const float v0 = kcd::fdec(kcd::wave_min_u32(kcd::ford(mn[a])));
@@ -412,16 +432,22 @@ __global__ __launch_bounds__(WG) void k_tighten_wide(TightenArgs A) {
 }
 
 template <int D>
-inline bool launch_wide(int S, int NG, bool refs, const TightenArgs &A, int grid, size_t lds,
-                        hipStream_t st) {
+inline bool launch_wide(int S, int NG, bool cap, bool refs, const TightenArgs &A, int grid,
+                        size_t lds, hipStream_t st) {
   if constexpr (D >= 1 && D <= 8) {
-#define KCT_WIDE(SV, NGV)                                                   \
-  if (S == SV && NG == NGV) {                                              \
-    if (refs)                                                              \
-      k_tighten_wide<D, SV, NGV, true><<<grid, WG, lds, st>>>(A);          \
-    else                                                                   \
-      k_tighten_wide<D, SV, NGV, false><<<grid, WG, lds, st>>>(A);         \
-    return true;                                                           \
+#define KCT_WIDE(SV, NGV)                                                        \
+  if (S == SV && NG == NGV) {                                                   \
+    if (cap && SV <= 8) {                                                       \
+      if (refs)                                                                 \
+        k_tighten_wide<D, SV, NGV, true, SV <= 8><<<grid, WG, lds, st>>>(A);    \
+      else                                                                      \
+        k_tighten_wide<D, SV, NGV, false, SV <= 8><<<grid, WG, lds, st>>>(A);   \
+    } else if (refs) {                                                          \
+      k_tighten_wide<D, SV, NGV, true, false><<<grid, WG, lds, st>>>(A);        \
+    } else {                                                                    \
+      k_tighten_wide<D, SV, NGV, false, false><<<grid, WG, lds, st>>>(A);       \
+    }                                                                           \
+    return true;                                                                \
   }
     KCT_WIDE_VARIANTS(KCT_WIDE)
 #undef KCT_WIDE
