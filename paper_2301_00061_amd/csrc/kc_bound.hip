@@ -276,7 +276,8 @@ kc_status kc_launch_bound(kc_handle *h, const kc_points *p, int mode, int n_node
                           int k_max, const int32_t *box_off, const float *lo, const float *hi,
                           float *val_raw, double *val_bound, int64_t *argmax, int64_t *cand,
                           const kc_tile &t0, hipStream_t st, void *fixed_scratch,
-                          size_t fixed_bytes, float cut, const double *floor) {
+                          size_t fixed_bytes, float cut, const double *floor,
+                          const float *wit_x, const int64_t *wit_id) {
   const bool point = mode == 1;
   const bool with_cand = cand != nullptr && !point;
   kc_tile t = t0;
@@ -347,6 +348,8 @@ kc_status kc_launch_bound(kc_handle *h, const kc_points *p, int mode, int n_node
   A.cut = cut;
   A.dead = nullptr;
   A.floor = point ? floor : nullptr;
+  A.wit_x = point && cut < INFINITY ? wit_x : nullptr;
+  A.wit_id = point && cut < INFINITY ? wit_id : nullptr;
   A.frel = 2.0 * kc_rel_margin(p->d);
   A.fabs_ = 2.0 * kc_abs_margin(p->d);
   A.gW = A.gC = nullptr;
@@ -558,6 +561,15 @@ extern "C" kc_status kc_objective_screen(kc_handle *h, const kc_points *pts, int
     return kc_launch_bound(h, pts, 1, n_sets, n_sets * k, k, nullptr, centers, centers, nullptr,
                            obj, argmax, nullptr, t, (hipStream_t)stream, nullptr, 0, cut, floor);
   });
+}
+
+kc_status kc_objective_screen_witness(kc_handle *h, const kc_points *pts, int n_sets, int k,
+                                      const float *centers, float cut, const double *floor,
+                                      const float *wit_x, const int64_t *wit_id, double *obj,
+                                      int64_t *argmax, hipStream_t st) {
+  const kc_tile t = kc_objective_tile(h, pts, n_sets, k, nullptr);
+  return kc_launch_bound(h, pts, 1, n_sets, n_sets * k, k, nullptr, centers, centers, nullptr, obj,
+                         argmax, nullptr, t, st, nullptr, 0, cut, floor, wit_x, wit_id);
 }
 
 extern "C" kc_status kc_objective(kc_handle *h, const kc_points *pts, int32_t n_sets, int32_t k,

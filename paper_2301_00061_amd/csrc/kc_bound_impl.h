@@ -47,6 +47,11 @@ struct BoundArgs {
   // set's float32 maximum reaches, so tiles strictly below it are skipped
   const double *floor;
   double frel, fabs_;
+  // POINT screening (nullable): per set one sample (coordinates [n_nodes][d]
+  // and its index in x); a set whose value at it exceeds the cut is settled
+  // at that value before any tile
+  const float *wit_x;
+  const int64_t *wit_id;
   // tile decisions: per node the largest W and per box the least cw any
   // wavefront has published (order-preserving encodings; null = no sharing)
   uint32_t *gW, *gC;

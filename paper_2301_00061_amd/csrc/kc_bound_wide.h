@@ -97,6 +97,38 @@ __global__ __launch_bounds__(WG) void k_bound_wide(BoundArgs A) {
     Wg = fmaxf(Wg, ff);
   }
   uint64_t deadm = __ballot(lane < NG && s_dead0[lane < NG ? lane : 0] != 0);  // screening
+  if constexpr (POINT) {
+    // the witness sample of each set, with the per-sample operations: a
+    // value above the cut settles the set there (wavefront 0 folds its key)
+    if (A.wit_x && A.dead) {
+      float v = INFINITY;
+      int64_t wid = -1;
+      if (cvalid) {
+        wid = A.wit_id[m0 + cj];
+        if (wid >= 0 && wid < A.n) {
+          const float *B = smem + cj * per_node + ck * 2 * DM;
+          const float *wx = A.wit_x + (int64_t)(m0 + cj) * D;
+          float acc = 0.f;
+#pragma unroll
+          for (int a = 0; a < DM; ++a) {
+            const float t = wx[a] - B[2 * a];
+            acc = (a == 0) ? t * t : __builtin_fmaf(t, t, acc);
+          }
+          v = acc;
+        }
+      }
+      v = kcd::group_min(v, KP);
+      const bool kill = cvalid && ck == 0 && wid >= 0 && wid < A.n && v > A.cut;
+      const uint64_t km = __ballot(kill);
+#pragma unroll
+      for (int jn = 0; jn < NG; ++jn)
+        if ((km >> (jn << lg)) & 1ull) deadm |= 1ull << jn;
+      if (kill && wave == 0) {
+        const uint64_t key = kcd::key_max(v, (uint32_t)wid);
+        if (key > s_key[0][cj]) s_key[0][cj] = key;
+      }
+    }
+  }
   uint64_t live = 0;   // bit jn: node jn exists
 #pragma unroll
   for (int jn = 0; jn < NG; ++jn)
@@ -150,6 +182,7 @@ __global__ __launch_bounds__(WG) void k_bound_wide(BoundArgs A) {
     const bool refresh = (tick++ & 15) == 0;
     const int64_t wb = base - lane_off + (int64_t)wave * 64 * S;
     if (wb >= s_hi) continue;  // no sample of this wavefront lies in the split (uniform)
+    if (POINT && !(live & ~deadm)) break;  // every set of the workgroup settled (uniform)
     float tlo[DM], thi[DM];
 #pragma unroll
     for (int a = 0; a < DM; ++a) {

@@ -88,7 +88,16 @@ kc_status kc_launch_bound(kc_handle *h, const kc_points *pts, int mode, int n_no
                           const float *hi, float *val_raw, double *val_bound, int64_t *argmax,
                           int64_t *cand, const kc_tile &t, hipStream_t st,
                           void *fixed_scratch = nullptr, size_t fixed_bytes = 0,
-                          float cut = INFINITY, const double *floor = nullptr);
+                          float cut = INFINITY, const double *floor = nullptr,
+                          const float *wit_x = nullptr, const int64_t *wit_id = nullptr);
+// kc_objective_screen with a witness sample per set (device: coordinates
+// [n_sets][d] and the sample's index in pts, negative = none): a set whose
+// float32 value at its witness exceeds cut is settled at that value before
+// any tile is read. Arguments are not validated (the solver's own calls).
+kc_status kc_objective_screen_witness(kc_handle *h, const kc_points *pts, int n_sets, int k,
+                                      const float *centers, float cut, const double *floor,
+                                      const float *wit_x, const int64_t *wit_id, double *obj,
+                                      int64_t *argmax, hipStream_t st);
 // Takes the device address of kc_lower_bound_noalloc's static scratch array
 // for the current device (kc_bound.hip); called by kc_create with h->device
 // current.

@@ -1488,10 +1488,12 @@ struct Solver {
       const size_t i0 = (size_t)R[g].first, gn = (size_t)(R[g].second - R[g].first);
       const kc_points p = pts_of(ev[i0]);
       // each set's centers lie in its node's boxes, so the node's lower
-      // bound is a lower bound of the set's objective
-      s = kc_objective_screen(h, &p, (int)gn, K, dxy + i0 * K * D, screen_cut(),
-                              out.dp<double>(o_lb) + i0, out.dp<double>(o_obj) + i0,
-                              out.dp<int64_t>(o_oam) + i0, (void *)st);
+      // bound is a lower bound of the set's objective; the node's lower-bound
+      // sample (farthest from its boxes) is the set's witness
+      s = kc_objective_screen_witness(h, &p, (int)gn, K, dxy + i0 * K * D, screen_cut(),
+                                      out.dp<double>(o_lb) + i0, dxy + ((size_t)ne * K + i0) * D,
+                                      ids + (size_t)ne * K + i0, out.dp<double>(o_obj) + i0,
+                                      out.dp<int64_t>(o_oam) + i0, st);
       if (s) return s;
       res->passes++;
       res->obj_evals += p.n * (int64_t)gn * K;

@@ -345,12 +345,14 @@ static std::vector<kc_tile> tighten_variants(int d, int kc, bool single, int k_m
       for (int m : {1, 2}) v.push_back({m * SD, 2, 0, 1});
     const int lg = lg_kp(k_max);
 // wide tiles: grids of 8 (bpc 0), 3, 16, 32 or 64 workgroups per compute unit
-// (smaller splits balance uneven work, fewer are resident at once), or 4
-// with registers capped at four wavefronts per SIMD (bpc 4, S <= 8)
-#define KCT_WV(SV, NGV)                        \
-  if ((NGV << lg) <= 64) {                     \
-    for (int g : {0, 3, 16, 32, 64}) v.push_back({SV, NGV, g, 2}); \
-    if (SV <= 8) v.push_back({SV, NGV, 4, 2}); \
+// (smaller splits balance uneven work, fewer are resident at once); bpc
+// 1000 + g: a grid of g per compute unit with registers capped at four
+// wavefronts per SIMD (S <= 8)
+#define KCT_WV(SV, NGV)                                                 \
+  if ((NGV << lg) <= 64) {                                              \
+    for (int g : {0, 3, 16, 32, 64}) v.push_back({SV, NGV, g, 2});     \
+    if (SV <= 8)                                                        \
+      for (int g : {4, 32, 64}) v.push_back({SV, NGV, 1000 + g, 2});  \
   }
     KCT_WIDE_VARIANTS(KCT_WV)
 #undef KCT_WV
@@ -409,7 +411,7 @@ static kc_status plan(kc_handle *h, const kc_points *pts, const kc_nodes *nodes,
   const int S = t.S;
   const int n_groups = (nodes->n_nodes + t.NG - 1) / t.NG;
   const int64_t units = (int64_t)n_groups * n_chunks;
-  const int64_t target = (int64_t)h->n_cu * (t.skip == 2 && t.bpc > 0 ? t.bpc : 8);
+  const int64_t target = (int64_t)h->n_cu * (t.skip == 2 && t.bpc % 1000 > 0 ? t.bpc % 1000 : 8);
   int64_t splits = (target + units - 1) / units;
   int64_t span = (pts->n + splits - 1) / splits;
   span = (span + WG * S - 1) / (WG * S) * (WG * S);

@@ -843,7 +843,7 @@ inline bool launch_kc(int S, int NG, int minw, int skip, bool refs, const Tighte
   namespace kct {                                                                       \
   bool NAME(int kc, int S, int NG, int minw, int skip, bool refs, const TightenArgs &A,   \
             int grid, size_t lds, hipStream_t st) {                                     \
-    if (skip == 2) return launch_wide<DV_>(S, NG, minw == 4, refs, A, grid, lds, st);   \
+    if (skip == 2) return launch_wide<DV_>(S, NG, minw >= 1000, refs, A, grid, lds, st);\
     switch (kc) {                                                                       \
       case 1: return launch_kc<DV_, 1>(S, NG, minw, skip, refs, A, grid, lds, st);      \
       case 2: return launch_kc<DV_, 2>(S, NG, minw, skip, refs, A, grid, lds, st);      \

@@ -624,10 +624,12 @@ def _tighten_tiles(d, k):
         kp = 1
         while kp < k:
             kp *= 2
-        # (grids of 8, 3, 16, 32 or 64 workgroups per compute unit; 4 with
-        # registers capped at four wavefronts per SIMD for S = 8)
+        # (grids of 8, 3, 16, 32 or 64 workgroups per compute unit; 1000 + g:
+        # g per compute unit with registers capped at four wavefronts per
+        # SIMD, for S = 8)
         tiles += [(S, NG, mw, 2) for S in (8, 16) for NG in (4, 8, 16) if NG * kp <= 64
-                  for mw in ((0, 3, 16, 32, 64, 4) if S <= 8 else (0, 3, 16, 32, 64))]
+                  for mw in ((0, 3, 16, 32, 64, 1004, 1032, 1064) if S <= 8
+                             else (0, 3, 16, 32, 64))]
     return tiles
 
 
