@@ -743,8 +743,12 @@ struct Solver {
   }
 
   // Over every open node, so the active samples stay valid for all of them;
-  // a subtree set no smaller than the result is then dropped.
-  kc_status reduce(const std::vector<Node *> &extra) {
+  // a subtree set no smaller than the result is then dropped. *kept: the
+  // number of samples the flags keep. When they would delete under 5%, the
+  // samples stay as they are (keeping redundant samples is always valid, and
+  // a compaction pass over all of them would cost more than it saves).
+  kc_status reduce(const std::vector<Node *> &extra, int64_t *kept) {
+    *kept = act.n;
     std::vector<const std::vector<float> *> los, his;
     std::vector<const Node *> ns;
     double beta = INFINITY;
@@ -777,13 +781,18 @@ struct Solver {
       return kc_fail(h, KC_ENOMEM, "sample buffers");
     const kc_nodes nd = dev_nodes(P);
     const kc_refs rf = dev_refs(P);
-    s = kc_reduce(h, &act, idx, &nd, P.refs ? &rf : nullptr, beta, alpha_ub, nullptr,
-                  xbuf[nxt].as<float>(), ibuf[nxt].as<uint32_t>(), X0->ld, out.dp<int64_t>(o_n), st);
+    s = kc_reduce_count(h, &act, &nd, P.refs ? &rf : nullptr, beta, alpha_ub, out.dp<int64_t>(o_n),
+                        st);
     if (s) return s;
     res->passes++;
     if ((s = download("reduce"))) return s;
     const int64_t n_out = *out.hp<int64_t>(o_n);
     if (n_out < 1) return KC_OK;  // keep the previous set (nothing left to bound)
+    *kept = n_out;
+    if (n_out * 20 > act.n * 19) return KC_OK;
+    if ((s = kc_reduce_compact(h, &act, idx, n_out, xbuf[nxt].as<float>(), ibuf[nxt].as<uint32_t>(),
+                               X0->ld, st)))
+      return s;
     cur = nxt;
     act.x = xbuf[cur].as<float>();
     act.n = n_out;
@@ -1261,10 +1270,11 @@ struct Solver {
         passes_since_sr = 0;
         tp = now_s();
         const int64_t before = act.n;
-        if ((s = reduce(live))) return s;
+        int64_t kept = before;
+        if ((s = reduce(live, &kept))) return s;
         ++sr_runs;
         const double cost = now_s() - tp;
-        if ((double)(before - act.n) < 0.01 * (double)before)
+        if ((double)(before - kept) < 0.01 * (double)before)
           sr_interval = std::min<int64_t>(sr_interval * 2, (int64_t)o.i_sr * 64);
         else
           sr_interval = o.i_sr;
