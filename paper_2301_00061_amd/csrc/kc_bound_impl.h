@@ -412,9 +412,11 @@ __global__ __launch_bounds__(WG) void k_obj64(Obj64Args A) {
 // Variants with tile decisions (k_bound_wide; attribute counts 1..8; usable
 // when NG << lg_kp <= 64).
 #define KCB_LB_TS_VARIANTS(X) X(8, 16) X(4, 16) X(8, 8) X(4, 8) X(4, 4) X(8, 1)
-#define KCB_PT_TS_VARIANTS(X) X(4, 16) X(8, 8) X(4, 8) X(4, 4) X(8, 1)
+#define KCB_PT_TS_VARIANTS(X) X(16, 16) X(8, 16) X(4, 16) X(32, 8) X(16, 8) X(8, 8) X(4, 8) X(4, 4) X(8, 1)
 #define KCB_CAND_TS_VARIANTS(X) \
-  X(4, 16, 4) X(2, 16, 4) X(4, 8, 4) X(4, 8, 8) X(2, 8, 8) X(4, 4, 8) X(4, 4, 16) X(2, 4, 16) X(4, 1, 64)
+  X(32, 16, 4) X(16, 16, 4) X(8, 16, 4) X(4, 16, 4) X(2, 16, 4) X(16, 8, 4) X(8, 8, 4) X(4, 8, 4) X(8, 8, 8) \
+  X(4, 8, 8) X(2, 8, 8) \
+  X(4, 4, 8) X(4, 4, 16) X(2, 4, 16) X(4, 1, 64)
 #define KCB_LB_TS_CASE(SV, NGV) \
   if (S == SV && NG == NGV) { k_bound_wide<DV, SV, NGV, 0, false><<<g, b, lds, st>>>(A); return KC_OK; }
 #define KCB_PT_TS_CASE(SV, NGV) \

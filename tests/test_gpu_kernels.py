@@ -675,10 +675,10 @@ _LB_TILES = [(8, 1), (4, 1), (2, 1), (4, 2), (4, 4), (2, 4), (4, 8), (2, 8), (2,
 _LB_TS_TILES = [(8, 16), (4, 16), (8, 8), (4, 8), (4, 4), (8, 1)]
 _CAND_TILES = [(2, 8, 4), (2, 4, 4), (2, 1, 4), (4, 4, 4), (4, 2, 4), (2, 4, 8), (2, 2, 8), (2, 1, 8),
                (4, 2, 8), (1, 4, 8), (1, 2, 16), (1, 1, 16), (1, 1, 64)]
-_CAND_TS_TILES = [(4, 16, 4), (2, 16, 4), (4, 8, 4), (4, 8, 8), (2, 8, 8), (4, 4, 8), (4, 4, 16),
-                  (2, 4, 16), (4, 1, 64)]
+_CAND_TS_TILES = [(32, 16, 4), (16, 16, 4), (8, 16, 4), (4, 16, 4), (2, 16, 4), (16, 8, 4), (8, 8, 4), (4, 8, 4),
+                  (8, 8, 8), (4, 8, 8), (2, 8, 8), (4, 4, 8), (4, 4, 16), (2, 4, 16), (4, 1, 64)]
 _PT_TILES = [(4, 1), (2, 4), (2, 8)]
-_PT_TS_TILES = [(4, 16), (8, 8), (4, 8), (4, 4), (8, 1)]
+_PT_TS_TILES = [(16, 16), (8, 16), (4, 16), (32, 8), (16, 8), (8, 8), (4, 8), (4, 4), (8, 1)]
 
 
 def _bound_key(d, cand, nn, k, n):
