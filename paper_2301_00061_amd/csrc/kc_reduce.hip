@@ -14,8 +14,10 @@
 namespace kcr {
 
 constexpr int WG = 256;
-constexpr int PER = 4;  // samples per lane
-constexpr int TILE = WG * PER;
+// samples per lane: 16 for 1..4 attributes (fewer workgroups, fewer tile
+// decisions per sample), else 4; a workgroup's tile is WG * per_lane(D)
+constexpr int per_lane(int D) { return D >= 1 && D <= 4 ? 16 : 4; }
+inline int64_t tile_of(int d) { return (int64_t)WG * per_lane(d <= 8 ? d : 0); }
 
 struct FlagArgs {
   const float *x;
@@ -181,6 +183,7 @@ __device__ __forceinline__ void classify_nodes(const FlagArgs &A, int g0, int lg
 template <int D, bool TS>
 __global__ __launch_bounds__(WG) void k_reduce_flags(FlagArgs A) {
   constexpr int DM = D ? D : 16;
+  constexpr int PER = per_lane(D), TILE = WG * PER;
   const int dd = D ? D : A.d;
   __shared__ uint32_t s_cnt[WG / 64];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -191,11 +194,14 @@ __global__ __launch_bounds__(WG) void k_reduce_flags(FlagArgs A) {
   for (int a = 0; a < DM; ++a) {
     const float *p = A.x + (int64_t)a * A.ld + s0;
     if (a < dd && s0 + PER <= A.n && ((uintptr_t)p & 15) == 0) {
-      const float4 v = *reinterpret_cast<const float4 *>(p);
-      xv[0][a] = v.x;
-      xv[1][a] = v.y;
-      xv[2][a] = v.z;
-      xv[3][a] = v.w;
+#pragma unroll
+      for (int q = 0; q < PER / 4; ++q) {
+        const float4 v = reinterpret_cast<const float4 *>(p)[q];
+        xv[4 * q][a] = v.x;
+        xv[4 * q + 1][a] = v.y;
+        xv[4 * q + 2][a] = v.z;
+        xv[4 * q + 3][a] = v.w;
+      }
     } else {
 #pragma unroll
       for (int j = 0; j < PER; ++j) xv[j][a] = (a < dd && s0 + j < A.n) ? p[j] : 0.f;
@@ -271,7 +277,7 @@ __global__ __launch_bounds__(WG) void k_reduce_flags(FlagArgs A) {
 }
 
 // Tile offsets in two levels: k_scan_local scans SCAN_BLOCK tile counts per
-// workgroup (block-local exclusive offsets, at most 2^21, and the block's
+// workgroup (block-local exclusive offsets, at most 2^23, and the block's
 // total); k_reduce_scan then scans the block totals in one workgroup. A
 // tile's output position is its block's offset plus its local offset.
 constexpr int SCAN_PER = 8;
@@ -341,6 +347,7 @@ __global__ __launch_bounds__(WG) void k_reduce_scatter(const float *x, int64_t n
                                                        float *x_out, uint32_t *idx_out,
                                                        int64_t ld_out) {
   constexpr int DM = D ? D : 16;
+  constexpr int PER = per_lane(D), TILE = WG * PER;
   const int dd = D ? D : d;
   __shared__ uint32_t s_w[PER][WG / 64];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -431,7 +438,7 @@ static bool reduce_tiles(kc_handle *h, int d) {
 static kc_status count_impl(kc_handle *h, const kc_points *in, const kc_nodes *open,
                             const kc_refs *refs, double beta, double alpha, uint8_t *keep,
                             int64_t *n_out, hipStream_t st) {
-  const int64_t n_tiles = (in->n + TILE - 1) / TILE;
+  const int64_t n_tiles = (in->n + tile_of(in->d) - 1) / tile_of(in->d);
   const int64_t n_blocks = (n_tiles + SCAN_BLOCK - 1) / SCAN_BLOCK;
   const size_t keep_bytes = keep ? 0 : (((size_t)in->n + 255) & ~(size_t)255);
   const size_t cnt_bytes = (((size_t)n_tiles * 4) + 255) & ~(size_t)255;
@@ -500,7 +507,7 @@ static kc_status compact_impl(kc_handle *h, const kc_points *in, const uint32_t 
                               hipStream_t st) {
   KC_RETURN_IF(h->red.x != in->x || h->red.n != in->n || h->red.scratch != h->scratch, h,
                KC_EINVAL, "compaction without a matching count of the same samples");
-  const int64_t n_tiles = (in->n + TILE - 1) / TILE;
+  const int64_t n_tiles = (in->n + tile_of(in->d) - 1) / tile_of(in->d);
   char *scr = (char *)h->red.scratch;
   const uint8_t *kf = keep ? keep : (const uint8_t *)scr;
   const uint32_t *toff = (const uint32_t *)(scr + h->red.keep_bytes + h->red.cnt_bytes);
