@@ -719,9 +719,10 @@ struct Solver {
   // keeps).
   bool can_reduce(const std::vector<Node *> &extra) const {
     const double thr = prune_thr();
-    double beta = INFINITY;
-    for (const Node *m : heap)
-      if (m->lb < thr) beta = std::min(beta, m->lb);
+    // least bound among the open nodes below the threshold: the heap's front
+    // (a scan of the whole heap every pass would cost more than the kernels
+    // once the open set holds millions of nodes)
+    double beta = !heap.empty() && heap.front()->lb < thr ? heap.front()->lb : INFINITY;
     for (const Node *m : extra) beta = std::min(beta, m->lb);
     if (!(beta > 0) || !std::isfinite(beta)) return false;
     auto small_box = [&](const Node *m) {
