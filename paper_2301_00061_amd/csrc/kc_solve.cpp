@@ -738,6 +738,10 @@ struct Solver {
     };
     for (const Node *m : extra)
       if (!small_box(m)) return false;
+    // the least-bound nodes (the top of the heap) first: they are the likeliest
+    // to keep a large box, which ends the scan of the open set at once
+    for (size_t i = 0; i < heap.size() && i < 64; ++i)
+      if (heap[i]->lb < thr && !small_box(heap[i])) return false;
     for (const Node *m : heap)
       if (m->lb < thr && !small_box(m)) return false;
     return true;
