@@ -219,6 +219,7 @@ struct Solver {
   // wall time per phase (reported with verbose)
   double t_tighten = 0, t_reduce = 0, t_branch = 0, t_bound = 0;
   int64_t sr_interval = 0, sr_runs = 0;
+  int64_t trigger_calls = 0;  // reduction-trigger calls on a very large open set
   int64_t n_bounded = 0, n_bounded_pruned = 0;  // bounded nodes, and those the bound prunes
   // subtree sample sets: bytes held and the cap on them; measured cost of a
   // one-node reduction per sample of the node
@@ -717,7 +718,7 @@ struct Solver {
   // diagonal away, so a node none of whose boxes has a squared half-diagonal
   // below beta keeps every sample (and the reduction keeps what any node
   // keeps).
-  bool can_reduce(const std::vector<Node *> &extra) const {
+  bool can_reduce(const std::vector<Node *> &extra) {
     const double thr = prune_thr();
     // least bound among the open nodes below the threshold: the heap's front
     // (a scan of the whole heap every pass would cost more than the kernels
@@ -742,6 +743,9 @@ struct Solver {
     // to keep a large box, which ends the scan of the open set at once
     for (size_t i = 0; i < heap.size() && i < 64; ++i)
       if (heap[i]->lb < thr && !small_box(heap[i])) return false;
+    // a scan of a very large open set runs on every 16th call only (a
+    // reduction that could already run waits a few passes; none is unsafe)
+    if (heap.size() > 65536 && (++trigger_calls & 15) != 0) return false;
     for (const Node *m : heap)
       if (m->lb < thr && !small_box(m)) return false;
     return true;
