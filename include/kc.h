@@ -363,8 +363,11 @@ typedef struct {
 } kc_result;
 
 /* Algorithm 1 on the device-resident samples `pts` (synchronous; uses its own
- * stream). The certified objective is evaluated in float64 over the original
- * samples; lb is a rigorous lower bound. res is host memory. */
+ * stream). During the search the best candidate set's rigorous float32 upper
+ * bound prunes; its objective is evaluated in float64 over the original
+ * samples once, when the search ends for any reason (gap closed, open set
+ * exhausted, node or time limit). lb is a rigorous lower bound. res is host
+ * memory. */
 kc_status kc_solve(kc_handle *h, const kc_points *pts, const kc_opts *opts, kc_result *res);
 
 #ifdef __cplusplus
